@@ -317,9 +317,12 @@ int orc_relax_cell(const orc_cfg *c, const double *fstar, double lam, double *fo
 
 /* ----------------------------------------------------------- transport */
 
+/* minmod(a, b) = 0 when a and b differ in sign or one is zero, otherwise the
+ * argument of smaller magnitude.  The sign test is done on the signs (not on
+ * the product a*b, which underflows to zero for tiny tail values). */
 static double orc_minmod(double a, double b)
 {
-    if (a * b <= 0.0) return 0.0;
+    if (!((a > 0.0 && b > 0.0) || (a < 0.0 && b < 0.0))) return 0.0;
     return a > 0.0 ? fmin(a, b) : fmax(a, b);
 }
 
