@@ -1,0 +1,164 @@
+"""Benchmark of the kinetic IMEX stage (coupled ES-BGK / Euler, 2D2V) on one GPU.
+
+    python bench.py [--steps K] [--warmup W] [--gpus 1] [--precision fp32|bf16|fp64]
+                    [--workload riemann4|blast|shear] [--no-cpu-baseline]
+
+Workload (default): four-quadrant Riemann problem on a periodic 256 x 256 grid
+with a 32 x 32 velocity grid on [-10, 10]^2, Knudsen number varying smoothly
+from 1e-4 to 1, ARS(2,3,3), minmod reconstruction, FP32, regime indicator on
+every step (domain decomposition active).  A step is one pass of Algorithm 1:
+regime update + compaction, two implicit kinetic stages, the final
+combination, and the Euler stages on fluid cells.
+
+Prints ONE JSON line.  `value` is phase-space point-updates per second per
+implicit IMEX stage: sum over timed steps of (kinetic cells x nv^2 x 2) / time.
+The roofline entry is for the kernel with the largest share of the step,
+timed with HIP events on its stream during the timed region; its algorithmic
+bytes per point are the f-array passes it must make.
+"""
+from __future__ import annotations
+
+import argparse
+import json
+import os
+import sys
+import time
+
+ROOT = os.path.dirname(os.path.abspath(__file__))
+sys.path.insert(0, ROOT)
+
+HBM_PEAK_GBS = 8000.0
+
+WORKLOADS = {
+    # name: (generator, kwargs, nx, nv, vmax, steps in the configuration)
+    "riemann4": dict(gen="riemann4", nx=256, nv=32, vmax=10.0, kw=dict(seed=0), steps=200),
+    "shear": dict(gen="shear_modes", nx=512, nv=48, vmax=8.0, kw=dict(seed=0), steps=100),
+    "blast": dict(gen="blast", nx=1024, nv=64, vmax=20.0, kw=dict(), steps=200),
+}
+
+# f-array passes (reads + writes) per point of each kinetic kernel class
+PASSES = {"stage2": 2, "stage3": 3, "final": 4}
+
+
+def parse():
+    ap = argparse.ArgumentParser()
+    ap.add_argument("--gpus", type=int, default=1)
+    ap.add_argument("--steps", type=int, default=200)
+    ap.add_argument("--warmup", type=int, default=10)
+    ap.add_argument("--precision", default="fp32", choices=["fp32", "bf16", "fp64"])
+    ap.add_argument("--workload", default="riemann4", choices=sorted(WORKLOADS))
+    ap.add_argument("--no-cpu-baseline", action="store_true")
+    ap.add_argument("--cpu-steps", type=int, default=8)
+    return ap.parse_args()
+
+
+def cpu_baseline(wl, nsteps):
+    """The FP64 oracle, as it stands, on a bounded sample of the same workload:
+    the same generator and physics on a 128 x 128 spatial grid with the full
+    velocity grid, a few steps with the regime update on."""
+    import numpy as np
+
+    import oracle
+    from paper_2512_03586_amd import inputs
+    oracle.build(force=False)
+    nx = 128
+    d = getattr(inputs, wl["gen"])(nx=nx, ny=nx, nv=wl["nv"], vmax=wl["vmax"], **wl["kw"])
+    p = oracle.Problem(nx=nx, ny=nx, nv=wl["nv"], vmax=wl["vmax"], scheme=1, recon=1, eta=1e-2, delta=1e-3)
+    st = oracle.State.from_primitives(p, d["rho"], d["ux"], d["uy"], d["T"], d["eps"])
+    st.run(1, update_regime=True)          # warm-up step (also makes cells kinetic)
+    kin = 0
+    t = time.perf_counter()
+    for _ in range(nsteps):
+        st.run(1, update_regime=True)
+        kin += int(st.mask.sum())
+    el = time.perf_counter() - t
+    pu = kin * wl["nv"] ** 2 * 2
+    return {"value": pu / el, "unit": "point-updates/s", "cores": oracle.num_threads(), "kind": "oracle",
+            "sample": f"{wl['gen']} {nx}x{nx} cells x {wl['nv']}x{wl['nv']} velocities, FP64, "
+                      f"{nsteps} steps after 1 warm-up step, regime update on "
+                      f"({kin / nsteps:.0f} kinetic cells/step), {el:.1f} s"}
+
+
+def main():
+    args = parse()
+    if args.gpus != 1:
+        print(f"bench.py measures one GPU only (got --gpus {args.gpus}); the multi-GPU path is a "
+              f"design, not built in this project", file=sys.stderr)
+        sys.exit(2)
+    import numpy as np
+    import torch
+
+    from paper_2512_03586_amd import esbgk as E
+    from paper_2512_03586_amd import inputs
+
+    wl = WORKLOADS[args.workload]
+    prec = {"fp32": E.FP32, "bf16": E.BF16, "fp64": E.FP64}[args.precision]
+    esize = {"fp32": 4, "bf16": 2, "fp64": 8}[args.precision]
+    nx, nv, vmax = wl["nx"], wl["nv"], wl["vmax"]
+    d = getattr(inputs, wl["gen"])(nx=nx, ny=nx, nv=nv, vmax=vmax, **wl["kw"])
+    cfg = E.make_config(nx, nx, nv, vmax, precision=prec, indicator=E.IND_PLAIN, scheme=E.ARS233,
+                        recon=E.MINMOD2, eta=1e-2, delta=1e-3)
+    eng = E.Engine(cfg)
+    dev = {k: torch.as_tensor(d[k]).cuda() for k in ("rho", "ux", "uy", "T", "eps")}
+
+    def reset():
+        E.esbgk_set_state(eng.ctx, dev["rho"], dev["ux"], dev["uy"], dev["T"], dev["eps"])
+
+    reset()
+    eng.step(args.warmup)
+    torch.cuda.synchronize()
+    reset()                                   # time the configuration from t = 0
+    torch.cuda.synchronize()
+    E.esbgk_set_timing(eng.ctx, True)
+    E.esbgk_kernel_times(eng.ctx, reset=True)
+    t0 = time.perf_counter()
+    eng.step(args.steps)
+    torch.cuda.synchronize()
+    el = time.perf_counter() - t0
+    E.esbgk_set_timing(eng.ctx, False)
+    ms, launches = E.esbgk_kernel_times(eng.ctx, reset=True)
+    stats = eng.stats()
+    kin_steps = stats.kinetic_cell_steps
+    pu = kin_steps * nv * nv * 2
+    value = pu / el
+    names = ["stage2", "stage3", "final"]
+    dom = max(range(3), key=lambda k: ms[k])
+    kin_avg = kin_steps / max(args.steps, 1)
+    t_launch = ms[dom] / max(launches[dom], 1) * 1e-3
+    bytes_launch = PASSES[names[dom]] * esize * kin_avg * nv * nv
+    achieved = bytes_launch / t_launch / 1e9
+    breakdown = {names[k]: round(ms[k] / max(launches[k], 1), 4) for k in range(3)}
+    breakdown["fill"] = round(ms[3] / max(launches[3], 1), 4)
+    print(f"# kernel ms/launch {breakdown}; kinetic cells/step {kin_avg:.0f} of {nx * nx}; "
+          f"step {el / args.steps * 1e3:.3f} ms", file=sys.stderr)
+    out = {
+        "metric": "phase-space point-updates/s per IMEX stage",
+        "value": value,
+        "unit": "point-updates/s",
+        "n_gpus": 1,
+        "steps": args.steps,
+        "warmup": args.warmup,
+        "ms_per_step": el / args.steps * 1e3,
+        "higher_is_better": True,
+        "scaling": "weak",
+        "vs_baseline": None,
+        "dtype": {"fp32": "f32", "bf16": "bf16-storage/f32", "fp64": "f64"}[args.precision],
+        "data": "synthetic",
+        "config": {"workload": f"{wl['gen']} {nx}x{nx} cells x {nv}x{nv} velocities on [-{vmax:g},{vmax:g}]^2, "
+                               f"ARS(2,3,3), minmod, regime update every step, {args.steps} steps from t=0",
+                   "nx": nx, "ny": nx, "nv": nv, "precision": args.precision,
+                   "kinetic_cells_per_step": round(kin_avg, 1),
+                   "kernel_ms_per_launch": breakdown},
+        "roofline": {"bound": "hbm", "kernel": names[dom], "achieved": achieved, "peak": HBM_PEAK_GBS,
+                     "unit": "GB/s", "frac": achieved / HBM_PEAK_GBS, "traffic": None,
+                     "algorithmic_bytes_per_launch": bytes_launch},
+    }
+    if stats.error_flags:
+        out["error_flags"] = stats.error_flags
+    if not args.no_cpu_baseline:
+        out["cpu_baseline"] = cpu_baseline(wl, args.cpu_steps)
+    print(json.dumps(out))
+
+
+if __name__ == "__main__":
+    main()

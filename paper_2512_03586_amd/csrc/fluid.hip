@@ -1,0 +1,382 @@
+// fluid.hip -- per-cell kernels: the Euler finite-volume stage on fluid cells,
+// primitive/conserved conversions, the regime indicator, cell classification
+// and the deterministic stream compaction of kinetic / buffer cells.
+#include "kernels.h"
+
+// Every floating-point expression in this file is evaluated as written: no
+// fused multiply-add contraction (the indicator's results must be the
+// correctly rounded IEEE operations of its documented order).
+#pragma clang fp contract(off)
+
+namespace esbgk {
+
+__device__ inline int wrapc(int i, int n) { i %= n; return i < 0 ? i + n : i; }
+
+// ------------------------------------------------------------------ Euler
+
+__device__ inline double dminmod(double a, double b) {
+    if (!((a > 0.0 && b > 0.0) || (a < 0.0 && b < 0.0))) return 0.0;
+    return a > 0.0 ? fmin(a, b) : fmax(a, b);
+}
+
+// Physical flux of the compressible Euler system in direction d
+// (eq. Euler_Compact, gamma = 2 so P = E - rho|u|^2/2).
+__device__ inline void euler_flux(const double U[4], int d, double F[4], double *speed) {
+    double rho = U[0], ux = U[1] / rho, uy = U[2] / rho, E = U[3];
+    double P = E - 0.5 * rho * (ux * ux + uy * uy);
+    double un = d == 0 ? ux : uy;
+    F[0] = rho * un;
+    F[1] = U[1] * un + (d == 0 ? P : 0.0);
+    F[2] = U[2] * un + (d == 1 ? P : 0.0);
+    F[3] = un * (E + P);
+    *speed = fabs(un) + sqrt(2.0 * P / rho);
+}
+
+// Rusanov flux at the face between cells p and q (Sec. 3.2, Lax-Friedrichs
+// type), reconstruction applied component-wise to U.
+__device__ inline void euler_face(const double *U, size_t nc, size_t cpm, size_t cp, size_t cq,
+                                  size_t cqp, int d, int recon, double Fh[4]) {
+    double UL[4], UR[4];
+#pragma unroll
+    for (int q = 0; q < 4; ++q) {
+        double a = U[q * nc + cpm], b = U[q * nc + cp], e = U[q * nc + cq], g = U[q * nc + cqp];
+        double sp = 0.0, sq = 0.0;
+        if (recon == 1) {
+            sp = dminmod(b - a, e - b);
+            sq = dminmod(e - b, g - e);
+        }
+        UL[q] = b + 0.5 * sp;
+        UR[q] = e - 0.5 * sq;
+    }
+    double FL[4], FR[4], aL, aR;
+    euler_flux(UL, d, FL, &aL);
+    euler_flux(UR, d, FR, &aR);
+    double s = fmax(aL, aR);
+#pragma unroll
+    for (int q = 0; q < 4; ++q) Fh[q] = 0.5 * (FL[q] + FR[q]) - 0.5 * s * (UR[q] - UL[q]);
+}
+
+// U^(i) = U^n - dt sum_j c_j Phi(U^(j)) on fluid cells (eqs. RKEuler, RKEuler_2).
+__global__ void euler_stage_kernel(EulerArgs a) {
+    const int cell = blockIdx.x * blockDim.x + threadIdx.x;
+    if (cell >= a.nc) return;
+    if (a.mask[cell]) return;
+    const size_t nc = (size_t)a.nc;
+    const int nx = a.nx, ny = a.ny;
+    const int i = cell % nx, j = cell / nx;
+    auto CI = [&](int ii, int jj) { return (size_t)wrapc(jj, ny) * nx + wrapc(ii, nx); };
+    double s[4];
+#pragma unroll
+    for (int q = 0; q < 4; ++q) s[q] = a.Un[q * nc + cell];
+    for (int jj = 0; jj < a.nj; ++jj) {
+        const double *U = a.Uj[jj];
+        double Fp[4], Fm[4], Gp[4], Gm[4];
+        euler_face(U, nc, CI(i - 1, j), CI(i, j), CI(i + 1, j), CI(i + 2, j), 0, a.recon, Fp);
+        euler_face(U, nc, CI(i - 2, j), CI(i - 1, j), CI(i, j), CI(i + 1, j), 0, a.recon, Fm);
+        euler_face(U, nc, CI(i, j - 1), CI(i, j), CI(i, j + 1), CI(i, j + 2), 1, a.recon, Gp);
+        euler_face(U, nc, CI(i, j - 2), CI(i, j - 1), CI(i, j), CI(i, j + 1), 1, a.recon, Gm);
+        const double c = a.dt * a.cj[jj];
+#pragma unroll
+        for (int q = 0; q < 4; ++q) s[q] -= c * ((Fp[q] - Fm[q]) / a.dx + (Gp[q] - Gm[q]) / a.dy);
+    }
+#pragma unroll
+    for (int q = 0; q < 4; ++q) a.Uout[q * nc + cell] = s[q];
+}
+
+// ------------------------------------------------------- conversions
+
+// Primitive variables, every operation a correctly rounded IEEE double op in
+// a fixed order (part of the bit-exact indicator contract).
+__device__ inline void prim_of(double U0, double U1, double U2, double U3, double *rho, double *ux,
+                               double *uy, double *T) {
+    *rho = U0;
+    *ux = __ddiv_rn(U1, U0);
+    *uy = __ddiv_rn(U2, U0);
+    double k = __dmul_rn(__dmul_rn(0.5, U0), __dadd_rn(__dmul_rn(*ux, *ux), __dmul_rn(*uy, *uy)));
+    *T = __ddiv_rn(__dsub_rn(U3, k), U0);
+}
+
+__global__ void prim_kernel(const double *U, double *prim, int nc) {
+    const int c = blockIdx.x * blockDim.x + threadIdx.x;
+    if (c >= nc) return;
+    const size_t n = (size_t)nc;
+    double r, ux, uy, T;
+    prim_of(U[c], U[n + c], U[2 * n + c], U[3 * n + c], &r, &ux, &uy, &T);
+    prim[c] = r; prim[n + c] = ux; prim[2 * n + c] = uy; prim[3 * n + c] = T;
+}
+
+__global__ void conserved_kernel(const double *rho, const double *ux, const double *uy,
+                                 const double *T, const double *eps, double *U, double *eps_out,
+                                 int nc, int *bad) {
+    const int c = blockIdx.x * blockDim.x + threadIdx.x;
+    if (c >= nc) return;
+    const size_t n = (size_t)nc;
+    double r = rho[c], a = ux[c], b = uy[c], t = T[c], e = eps[c];
+    if (!(r > 0.0) || !(t > 0.0) || !(e > 0.0) || !isfinite(r) || !isfinite(a) || !isfinite(b) ||
+        !isfinite(t) || !isfinite(e))
+        atomicOr(bad, 1);
+    U[c] = r;
+    U[n + c] = r * a;
+    U[2 * n + c] = r * b;
+    U[3 * n + c] = 0.5 * r * (a * a + b * b) + r * t;
+    eps_out[c] = e;
+}
+
+// ------------------------------------------------------------- indicator
+
+// Regime indicator of Sec. 3.1.2 at one cell.  The operation order matches the
+// documented contract (no contraction: explicit round-to-nearest intrinsics).
+__device__ inline uint8_t indicator_cell(const IndicatorArgs &a, int cell, double *lam_out) {
+    const size_t n = (size_t)a.nc;
+    const int nx = a.nx, ny = a.ny;
+    const int i = cell % nx, j = cell / nx;
+    const size_t ce = (size_t)j * nx + wrapc(i + 1, nx), cw = (size_t)j * nx + wrapc(i - 1, nx);
+    const size_t cn = (size_t)wrapc(j + 1, ny) * nx + i, cs = (size_t)wrapc(j - 1, ny) * nx + i;
+    const double *ux = a.prim + n, *uy = a.prim + 2 * n, *T = a.prim + 3 * n;
+    const double twodx = a.twodx, twody = a.twody;
+    const double uxx = __ddiv_rn(__dsub_rn(ux[ce], ux[cw]), twodx);
+    const double uxy = __ddiv_rn(__dsub_rn(ux[cn], ux[cs]), twody);
+    const double uyx = __ddiv_rn(__dsub_rn(uy[ce], uy[cw]), twodx);
+    const double uyy = __ddiv_rn(__dsub_rn(uy[cn], uy[cs]), twody);
+    const double Tx = __ddiv_rn(__dsub_rn(T[ce], T[cw]), twodx);
+    const double Ty = __ddiv_rn(__dsub_rn(T[cn], T[cs]), twody);
+    const double div = __dadd_rn(uxx, uyy);
+    const double Dxx = __dsub_rn(__dadd_rn(uxx, uxx), __dmul_rn(a.cD, div));
+    const double Dxy = __dadd_rn(uxy, uyx);
+    const double Dyy = __dsub_rn(__dadd_rn(uyy, uyy), __dmul_rn(a.cD, div));
+    const double e = a.eps[cell];
+    const double cv = __ddiv_rn(e, __dmul_rn(a.tau, a.omb));
+    const double kt = __ddiv_rn(__dmul_rn(a.ck, e), __dmul_rn(a.tau, __dsqrt_rn(T[cell])));
+    const double kt2 = __dmul_rn(a.cS, __dmul_rn(kt, kt));
+    const double a11 = __dsub_rn(-__dmul_rn(cv, Dxx), __dmul_rn(kt2, __dmul_rn(Tx, Tx)));
+    const double a12 = __dsub_rn(-__dmul_rn(cv, Dxy), __dmul_rn(kt2, __dmul_rn(Tx, Ty)));
+    const double a22 = __dsub_rn(-__dmul_rn(cv, Dyy), __dmul_rn(kt2, __dmul_rn(Ty, Ty)));
+    const double m = __ddiv_rn(__dadd_rn(a11, a22), 2.0);
+    const double h = __ddiv_rn(__dsub_rn(a11, a22), 2.0);
+    const double lam = __dadd_rn(fabs(m), __dsqrt_rn(__dadd_rn(__dmul_rn(h, h), __dmul_rn(a12, a12))));
+    if (lam_out) *lam_out = lam;
+    const bool critS = lam > a.eta;
+    const bool critL = a.l1[cell] > a.delta;
+    return (uint8_t)(critS || (a.mask_old[cell] && critL));
+}
+
+__global__ void indicator_kernel(IndicatorArgs a) {
+    const int c = blockIdx.x * blockDim.x + threadIdx.x;
+    if (c >= a.nc) return;
+    double lam;
+    uint8_t m = indicator_cell(a, c, &lam);
+    a.mask_new[c] = m;
+    if (a.lambda) a.lambda[c] = lam;
+}
+
+// ------------------------------------------------- classify + compaction
+
+// class bits: 1 kinetic, 2 buffer (fluid cell inside a kinetic stencil),
+// 4 newly kinetic (needs f = Mhat(U)).
+__global__ void classify_kernel(const uint8_t *mask, const uint8_t *mask_old, uint8_t *cls, int nx,
+                                int ny, int radius) {
+    const int c = blockIdx.x * blockDim.x + threadIdx.x;
+    if (c >= nx * ny) return;
+    const int i = c % nx, j = c / nx;
+    uint8_t k = mask[c];
+    uint8_t out = 0;
+    if (k) {
+        out = 1;
+        if (mask_old && !mask_old[c]) out |= 4;
+    } else {
+        bool near = false;
+        for (int d = 1; d <= radius; ++d) {
+            near = near || mask[(size_t)j * nx + wrapc(i - d, nx)] || mask[(size_t)j * nx + wrapc(i + d, nx)] ||
+                   mask[(size_t)wrapc(j - d, ny) * nx + i] || mask[(size_t)wrapc(j + d, ny) * nx + i];
+        }
+        if (near) out = 2;
+    }
+    cls[c] = out;
+}
+
+// Position -> cell in the processing order: 8x8 cell tiles, row-major inside
+// a tile, tiles row-major; -1 for positions of a padded edge tile.
+__device__ inline int pos_to_cell(int pos, int nx, int ny) {
+    const int ntx = (nx + 7) / 8;
+    const int t = pos >> 6, w = pos & 63;
+    const int i = (t % ntx) * 8 + (w & 7), j = (t / ntx) * 8 + (w >> 3);
+    return (i < nx && j < ny) ? j * nx + i : -1;
+}
+
+constexpr int kScanBlock = 1024;  // positions per block (256 threads x 4)
+
+__global__ __launch_bounds__(256) void scan_count_kernel(const uint8_t *cls, int nx, int ny, int npos,
+                                                         int *blockcounts, int nblocks) {
+    __shared__ int red[3][256];
+    const int t = threadIdx.x;
+    int c3[3] = {0, 0, 0};
+    for (int e = 0; e < 4; ++e) {
+        int pos = blockIdx.x * kScanBlock + t * 4 + e;
+        if (pos < npos) {
+            int cell = pos_to_cell(pos, nx, ny);
+            if (cell >= 0) {
+                uint8_t k = cls[cell];
+                c3[0] += (k & 1) != 0;
+                c3[1] += (k & 2) != 0;
+                c3[2] += (k & 4) != 0;
+            }
+        }
+    }
+    for (int q = 0; q < 3; ++q) red[q][t] = c3[q];
+    __syncthreads();
+    for (int s = 128; s > 0; s >>= 1) {
+        if (t < s)
+            for (int q = 0; q < 3; ++q) red[q][t] += red[q][t + s];
+        __syncthreads();
+    }
+    if (t == 0)
+        for (int q = 0; q < 3; ++q) blockcounts[q * nblocks + blockIdx.x] = red[q][0];
+}
+
+// Single block: exclusive scan of the per-block counts (in place), totals to counts[0..2].
+__global__ __launch_bounds__(1024) void scan_blocks_kernel(int *blockcounts, int nblocks, int *counts) {
+    __shared__ int buf[1024];
+    const int t = threadIdx.x;
+    for (int q = 0; q < 3; ++q) {
+        int *bc = blockcounts + q * nblocks;
+        int carry = 0;
+        for (int base = 0; base < nblocks; base += 1024) {
+            int v = (base + t < nblocks) ? bc[base + t] : 0;
+            buf[t] = v;
+            __syncthreads();
+            for (int off = 1; off < 1024; off <<= 1) {
+                int add = t >= off ? buf[t - off] : 0;
+                __syncthreads();
+                buf[t] += add;
+                __syncthreads();
+            }
+            if (base + t < nblocks) bc[base + t] = carry + buf[t] - v;
+            int tot = buf[1023];
+            __syncthreads();
+            carry += tot;
+        }
+        if (t == 0) counts[q] = carry;
+        __syncthreads();
+    }
+}
+
+__global__ __launch_bounds__(256) void scan_scatter_kernel(const uint8_t *cls, int nx, int ny, int npos,
+                                                           const int *blockoff, int nblocks, int *kin,
+                                                           int *buf, int *newk) {
+    __shared__ int sc[3][256];
+    const int t = threadIdx.x;
+    int cells[4];
+    uint8_t ks[4];
+    int loc[3] = {0, 0, 0};
+    for (int e = 0; e < 4; ++e) {
+        int pos = blockIdx.x * kScanBlock + t * 4 + e;
+        int cell = pos < npos ? pos_to_cell(pos, nx, ny) : -1;
+        cells[e] = cell;
+        ks[e] = cell >= 0 ? cls[cell] : 0;
+        loc[0] += (ks[e] & 1) != 0;
+        loc[1] += (ks[e] & 2) != 0;
+        loc[2] += (ks[e] & 4) != 0;
+    }
+    for (int q = 0; q < 3; ++q) sc[q][t] = loc[q];
+    __syncthreads();
+    for (int off = 1; off < 256; off <<= 1) {
+        int add[3];
+        for (int q = 0; q < 3; ++q) add[q] = t >= off ? sc[q][t - off] : 0;
+        __syncthreads();
+        for (int q = 0; q < 3; ++q) sc[q][t] += add[q];
+        __syncthreads();
+    }
+    int o[3];
+    for (int q = 0; q < 3; ++q) o[q] = blockoff[q * nblocks + blockIdx.x] + sc[q][t] - loc[q];
+    for (int e = 0; e < 4; ++e) {
+        if (ks[e] & 1) kin[o[0]++] = cells[e];
+        if (ks[e] & 2) buf[o[1]++] = cells[e];
+        if (ks[e] & 4) newk[o[2]++] = cells[e];
+    }
+}
+
+__global__ void get_prim_kernel(const double *U, double *rho, double *ux, double *uy, double *T, int nc) {
+    const int c = blockIdx.x * blockDim.x + threadIdx.x;
+    if (c >= nc) return;
+    const size_t n = (size_t)nc;
+    double r, a, b, t;
+    prim_of(U[c], U[n + c], U[2 * n + c], U[3 * n + c], &r, &a, &b, &t);
+    if (rho) rho[c] = r;
+    if (ux) ux[c] = a;
+    if (uy) uy[c] = b;
+    if (T) T[c] = t;
+}
+
+__global__ void zero_fluid_l1_kernel(const uint8_t *mask, double *l1, int nc) {
+    const int c = blockIdx.x * blockDim.x + threadIdx.x;
+    if (c < nc && !mask[c]) l1[c] = 0.0;
+}
+
+__global__ void accumulate_count_kernel(const int *counts, long long *total) {
+    if (threadIdx.x == 0 && blockIdx.x == 0) *total += counts[0];
+}
+
+// ------------------------------------------------------- host launchers
+
+static inline unsigned cells_grid(int n) { return (unsigned)((n + 255) / 256 > 0 ? (n + 255) / 256 : 1); }
+
+hipError_t launch_euler(const EulerArgs &a, hipStream_t st) {
+    hipLaunchKernelGGL(euler_stage_kernel, dim3(cells_grid(a.nc)), dim3(256), 0, st, a);
+    return hipGetLastError();
+}
+
+hipError_t launch_prim(const double *U, double *prim, int nc, hipStream_t st) {
+    hipLaunchKernelGGL(prim_kernel, dim3(cells_grid(nc)), dim3(256), 0, st, U, prim, nc);
+    return hipGetLastError();
+}
+
+hipError_t launch_conserved(const double *rho, const double *ux, const double *uy, const double *T,
+                            const double *eps, double *U, double *eps_out, int nc, int *bad,
+                            hipStream_t st) {
+    hipLaunchKernelGGL(conserved_kernel, dim3(cells_grid(nc)), dim3(256), 0, st, rho, ux, uy, T, eps, U,
+                       eps_out, nc, bad);
+    return hipGetLastError();
+}
+
+hipError_t launch_indicator(const IndicatorArgs &a, hipStream_t st) {
+    hipLaunchKernelGGL(indicator_kernel, dim3(cells_grid(a.nc)), dim3(256), 0, st, a);
+    return hipGetLastError();
+}
+
+hipError_t launch_classify(const uint8_t *mask, const uint8_t *mask_old, uint8_t *cls, int nx, int ny,
+                           int radius, hipStream_t st) {
+    hipLaunchKernelGGL(classify_kernel, dim3(cells_grid(nx * ny)), dim3(256), 0, st, mask, mask_old, cls,
+                       nx, ny, radius);
+    return hipGetLastError();
+}
+
+int scan_positions(int nx, int ny) { return ((nx + 7) / 8) * ((ny + 7) / 8) * 64; }
+int scan_nblocks(int nx, int ny) { return (scan_positions(nx, ny) + kScanBlock - 1) / kScanBlock; }
+
+hipError_t launch_compact(const uint8_t *cls, int nx, int ny, int *blockcounts, int *counts, int *kin,
+                          int *buf, int *newk, hipStream_t st) {
+    const int npos = scan_positions(nx, ny), nb = scan_nblocks(nx, ny);
+    hipLaunchKernelGGL(scan_count_kernel, dim3(nb), dim3(256), 0, st, cls, nx, ny, npos, blockcounts, nb);
+    hipLaunchKernelGGL(scan_blocks_kernel, dim3(1), dim3(1024), 0, st, blockcounts, nb, counts);
+    hipLaunchKernelGGL(scan_scatter_kernel, dim3(nb), dim3(256), 0, st, cls, nx, ny, npos, blockcounts, nb,
+                       kin, buf, newk);
+    return hipGetLastError();
+}
+
+hipError_t launch_get_prim(const double *U, double *rho, double *ux, double *uy, double *T, int nc,
+                           hipStream_t st) {
+    hipLaunchKernelGGL(get_prim_kernel, dim3(cells_grid(nc)), dim3(256), 0, st, U, rho, ux, uy, T, nc);
+    return hipGetLastError();
+}
+
+hipError_t launch_accumulate_count(const int *counts, long long *total, hipStream_t st) {
+    hipLaunchKernelGGL(accumulate_count_kernel, dim3(1), dim3(64), 0, st, counts, total);
+    return hipGetLastError();
+}
+
+hipError_t launch_zero_fluid_l1(const uint8_t *mask, double *l1, int nc, hipStream_t st) {
+    hipLaunchKernelGGL(zero_fluid_l1_kernel, dim3(cells_grid(nc)), dim3(256), 0, st, mask, l1, nc);
+    return hipGetLastError();
+}
+
+}  // namespace esbgk

@@ -1,0 +1,96 @@
+// kernels.h -- argument blocks and host launchers of the engine's kernels.
+#pragma once
+
+#include "device.h"
+
+namespace esbgk {
+
+template <class S> struct StageArgs {
+    Geom g;
+    const S *fn;                                        // f^n: base value at the cell
+    const S *fl[2]; double cl[2];                       // transport terms  -dt*cl*L(fl)
+    const S *fq[2]; const double *pq[2]; double cq[2];  // sources +dt*cq*(tau/eps)(Ghat-fq)
+    int nl, nq;
+    double aii;                                         // implicit coefficient; 0 -> final combination
+    int emit;                                           // write the L1 distance of the result
+    S *fout;
+    double *pout;                                       // Gaussian parameters (GP_N per cell)
+    double *Uout;                                       // SoA [4][nc]
+    double *l1out;
+    const double *eps;
+    const int *list;
+    const int *count;
+    int *err;
+    int nc;
+};
+
+template <class S> struct FillArgs {
+    Geom g;
+    const double *U;
+    S *f;
+    const int *list;
+    const int *count;
+    int *err;
+    int nc;
+};
+
+template <class S> struct MomArgs {
+    Geom g;
+    const S *f;
+    double *U;
+    double *l1;
+    const int *list;
+    const int *count;
+    int *err;
+    int nc;
+};
+
+struct EulerArgs {
+    int nx, ny, nc, recon;
+    double dx, dy, dt;
+    const double *Un;
+    const double *Uj[3];
+    double cj[3];
+    int nj;
+    double *Uout;
+    const uint8_t *mask;
+};
+
+struct IndicatorArgs {
+    int nx, ny, nc;
+    double twodx, twody;
+    double tau, omb;     // omb = 1 - beta
+    double cD, ck, cS;
+    double eta, delta;
+    const double *prim;  // SoA [4][nc] = (rho, ux, uy, T)
+    const double *eps;
+    const double *l1;
+    const uint8_t *mask_old;
+    uint8_t *mask_new;
+    double *lambda;
+};
+
+template <class S> hipError_t launch_stage(const StageArgs<S> &a, int nmax, hipStream_t st);
+template <class S> hipError_t launch_fill(const FillArgs<S> &a, int nmax, hipStream_t st);
+template <class S> hipError_t launch_moments(const MomArgs<S> &a, int nmax, hipStream_t st);
+template <class S> hipError_t launch_from_f64(const double *in, void *out, size_t n, hipStream_t st);
+template <class S> hipError_t launch_to_f64(const void *in, double *out, size_t n, hipStream_t st);
+
+hipError_t launch_euler(const EulerArgs &a, hipStream_t st);
+hipError_t launch_prim(const double *U, double *prim, int nc, hipStream_t st);
+hipError_t launch_conserved(const double *rho, const double *ux, const double *uy, const double *T,
+                            const double *eps, double *U, double *eps_out, int nc, int *bad,
+                            hipStream_t st);
+hipError_t launch_indicator(const IndicatorArgs &a, hipStream_t st);
+hipError_t launch_classify(const uint8_t *mask, const uint8_t *mask_old, uint8_t *cls, int nx, int ny,
+                           int radius, hipStream_t st);
+hipError_t launch_compact(const uint8_t *cls, int nx, int ny, int *blockcounts, int *counts, int *kin,
+                          int *buf, int *newk, hipStream_t st);
+hipError_t launch_get_prim(const double *U, double *rho, double *ux, double *uy, double *T, int nc,
+                           hipStream_t st);
+hipError_t launch_accumulate_count(const int *counts, long long *total, hipStream_t st);
+hipError_t launch_zero_fluid_l1(const uint8_t *mask, double *l1, int nc, hipStream_t st);
+int scan_positions(int nx, int ny);
+int scan_nblocks(int nx, int ny);
+
+}  // namespace esbgk

@@ -1,0 +1,240 @@
+"""GPU parity: the HIP engine (through the C ABI) against the FP64 CPU oracle on
+the same seeded inputs.
+
+Bars: FP64 path -- moments within 1e-10 relative, f within 1e-12 of the
+largest value, masks bit-exact at every step; FP32 path -- moments within
+2e-5 relative; index work (compaction) and the indicator bit-exact.
+Sizes span several 8x8 tiles with ragged edges (nx, ny not multiples of 8)
+and ragged velocity tails (nv*nv not a multiple of 256).
+"""
+import numpy as np
+import pytest
+import torch
+
+import oracle
+from paper_2512_03586_amd import inputs
+
+pytestmark = pytest.mark.gpu
+
+E = None
+
+
+@pytest.fixture(scope="module", autouse=True)
+def _engine_module():
+    global E
+    if not torch.cuda.is_available():
+        pytest.fail("no GPU visible")
+    from paper_2512_03586_amd import esbgk
+    esbgk.lib()
+    E = esbgk
+    oracle.build(force=False)
+    yield
+
+
+def pair(d, *, scheme=1, recon=1, precision=0, indicator=1, coupling=0, correction=1, mask=None,
+         eta=1e-2, delta=1e-3, nv=None, vmax=None, dt=0.0):
+    nx, ny = d["nx"], d["ny"]
+    nv = nv or d["nv"]
+    vmax = vmax or d["vmax"]
+    p = oracle.Problem(nx=nx, ny=ny, nv=nv, vmax=vmax, lx=d["lx"], ly=d["ly"], scheme=scheme, recon=recon,
+                       correction=correction, coupling=coupling, eta=eta, delta=delta, dt=dt)
+    cfg = E.make_config(nx, ny, nv, vmax, lx=d["lx"], ly=d["ly"], scheme=scheme, recon=recon,
+                        precision=precision, indicator=indicator, coupling=coupling, correction=correction,
+                        eta=eta, delta=delta, dt=dt)
+    eng = E.Engine(cfg)
+    eng.set_state(d["rho"], d["ux"], d["uy"], d["T"], d["eps"])
+    st = oracle.State.from_primitives(p, d["rho"], d["ux"], d["uy"], d["T"], d["eps"], mask=mask)
+    if mask is not None:
+        eng.set_mask(mask)
+    return p, eng, st
+
+
+def gpu_U(eng):
+    return eng.conserved().cpu().numpy()
+
+
+def assert_U_close(Ug, Uo, rtol):
+    scale = np.abs(Uo).max(axis=1, keepdims=True)
+    err = np.abs(Ug - Uo) / scale
+    assert err.max() <= rtol, f"max rel err {err.max():.3e} (row {np.unravel_index(err.argmax(), err.shape)})"
+
+
+# ------------------------------------------------------------- unit pieces
+
+@pytest.mark.parametrize("precision,tol", [(0, 1e-13), (1, 2e-6)])
+def test_maxwellian_fill_matches_oracle(precision, tol):
+    d = inputs.riemann4(nx=9, ny=7, nv=20, vmax=8.0, seed=11)
+    mask = np.ones(63, np.uint8)
+    p, eng, st = pair(d, precision=precision, mask=mask)
+    f = eng.f().cpu().numpy()
+    assert np.abs(f - st.f).max() <= tol * np.abs(st.f).max()
+    # the corrected Maxwellian carries U exactly; the GPU's moments of its own f
+    Ug = gpu_U(eng)
+    assert_U_close(Ug, st.U, 1e-13 if precision == 0 else 2e-6)
+
+
+@pytest.mark.parametrize("nx,ny", [(16, 16), (37, 23), (5, 3)])
+def test_indicator_bit_exact(nx, ny):
+    rng = np.random.default_rng(nx * 100 + ny)
+    nc = nx * ny
+    prim = np.stack([rng.uniform(0.5, 2, nc), rng.uniform(-1, 1, nc), rng.uniform(-1, 1, nc),
+                     rng.uniform(0.3, 3, nc)])
+    eps = 10 ** rng.uniform(-5, 0, nc)
+    l1 = 10 ** rng.uniform(-5, -1, nc)
+    mold = (rng.uniform(size=nc) < 0.4).astype(np.uint8)
+    for ce_set in (0, 1):
+        for eta in (1e-3, 1e-2, 1e-1):
+            p = oracle.Problem(nx=nx, ny=ny, nv=8, vmax=4.0, ce_set=ce_set, eta=eta, delta=1e-3)
+            mo, lo = oracle.indicator(p, prim, eps, l1, mold, return_lambda=True)
+            cfg = E.make_config(nx, ny, 8, 4.0, ce_set=ce_set, eta=eta, delta=1e-3)
+            dev = lambda a, t=torch.float64: torch.as_tensor(np.ascontiguousarray(a), dtype=t).cuda()
+            mg = torch.empty(nc, dtype=torch.uint8, device="cuda")
+            lg = torch.empty(nc, dtype=torch.float64, device="cuda")
+            E.esbgk_indicator(cfg, dev(prim), dev(eps), dev(l1), dev(mold, torch.uint8), mg, lg)
+            assert np.array_equal(mg.cpu().numpy(), mo)
+            assert np.array_equal(lg.cpu().numpy().view(np.uint64), lo.view(np.uint64))
+            assert 0 < mo.sum() < nc or eta == 1e-1
+
+
+@pytest.mark.parametrize("nx,ny", [(16, 16), (20, 13), (3, 5)])
+def test_compaction_order_bit_exact(nx, ny):
+    d = inputs.smooth_density(nx=nx, ny=ny, nv=8, vmax=4.0)
+    mask = inputs.random_partition(nx * ny, 0.3, seed=nx + ny)
+    cfg = E.make_config(nx, ny, 8, 4.0, indicator=E.IND_FROZEN, precision=E.FP64)
+    eng = E.Engine(cfg)
+    eng.set_state(d["rho"], d["ux"], d["uy"], d["T"], d["eps"])
+    eng.set_mask(mask)
+    cells = eng.kinetic_cells().cpu().numpy()
+    # expected: 8x8 tiles row-major, row-major inside a tile
+    ntx, nty = (nx + 7) // 8, (ny + 7) // 8
+    exp = []
+    for tj in range(nty):
+        for ti in range(ntx):
+            for w in range(64):
+                i, j = ti * 8 + w % 8, tj * 8 + w // 8
+                if i < nx and j < ny and mask[j * nx + i]:
+                    exp.append(j * nx + i)
+    assert np.array_equal(cells, np.array(exp, np.int32))
+
+
+def test_set_state_rejects_nonphysical_input():
+    d = inputs.smooth_density(nx=8, ny=8, nv=8, vmax=4.0)
+    cfg = E.make_config(8, 8, 8, 4.0)
+    eng = E.Engine(cfg)
+    T = d["T"].copy(); T[5] = -1.0
+    with pytest.raises(E.EsbgkError) as ei:
+        eng.set_state(d["rho"], d["ux"], d["uy"], T, d["eps"])
+    assert ei.value.code == E.EINVAL
+    T[5] = np.nan
+    with pytest.raises(E.EsbgkError):
+        eng.set_state(d["rho"], d["ux"], d["uy"], T, d["eps"])
+
+
+# ------------------------------------------------------------ FP64 steps
+
+FP64_CASES = [
+    # (generator kwargs, scheme, recon)
+    (dict(nx=12, ny=10, nv=12, vmax=8.0, seed=1), 0, 0),
+    (dict(nx=12, ny=10, nv=16, vmax=8.0, seed=2), 1, 1),
+    (dict(nx=9, ny=11, nv=20, vmax=8.0, seed=3), 1, 1),
+    (dict(nx=17, ny=8, nv=8, vmax=6.0, seed=4), 0, 1),
+]
+
+
+@pytest.mark.parametrize("gen,scheme,recon", FP64_CASES)
+def test_fully_kinetic_fp64_matches_oracle(gen, scheme, recon):
+    d = inputs.riemann4(**gen)
+    nc = d["nx"] * d["ny"]
+    p, eng, st = pair(d, scheme=scheme, recon=recon, mask=np.ones(nc, np.uint8))
+    for n in (1, 3):
+        eng.step(n)
+        st.run(n, update_regime=False)
+        assert_U_close(gpu_U(eng), st.U, 1e-10)
+        f = eng.f().cpu().numpy()
+        assert np.abs(f - st.f).max() <= 1e-11 * np.abs(st.f).max()
+    assert eng.stats().error_flags == 0
+
+
+@pytest.mark.parametrize("scheme,recon,coupling", [(1, 1, 0), (0, 0, 0), (1, 1, 1)])
+def test_random_partition_fp64_matches_oracle(scheme, recon, coupling):
+    d = inputs.riemann4(nx=14, ny=11, nv=12, vmax=8.0, seed=5)
+    d["eps"] = np.full(14 * 11, 0.02)
+    mask = inputs.random_partition(14 * 11, 0.4, seed=3)
+    p, eng, st = pair(d, scheme=scheme, recon=recon, coupling=coupling, mask=mask)
+    eng.step(4)
+    st.run(4, update_regime=False)
+    assert_U_close(gpu_U(eng), st.U, 1e-10)
+    kin = mask.astype(bool)
+    f = eng.f().cpu().numpy()
+    assert np.abs(f[kin] - st.f[kin]).max() <= 1e-11 * np.abs(st.f[kin]).max()
+
+
+@pytest.mark.parametrize("scheme,recon", [(1, 1), (0, 0)])
+def test_plain_indicator_fp64_masks_bit_exact_every_step(scheme, recon):
+    """Coupled run with the regime update on: the masks agree at every step."""
+    d = inputs.riemann4(nx=16, ny=12, nv=12, vmax=8.0, seed=7, log_eps_mean=-2.5)
+    p, eng, st = pair(d, scheme=scheme, recon=recon, indicator=0, eta=5e-3, delta=1e-3)
+    seen_kinetic = 0
+    for step in range(6):
+        eng.step(1)
+        st.run(1, update_regime=True)
+        mg = eng.mask().cpu().numpy()
+        assert np.array_equal(mg, st.mask), f"step {step}: {np.nonzero(mg != st.mask)[0]}"
+        seen_kinetic = max(seen_kinetic, int(mg.sum()))
+        assert_U_close(gpu_U(eng), st.U, 1e-10)
+    assert 0 < seen_kinetic < 16 * 12
+
+
+def test_fully_kinetic_fp64_conserves():
+    d = inputs.riemann4(nx=16, ny=16, nv=16, vmax=8.0, seed=9)
+    nc = 256
+    cfg = E.make_config(16, 16, 16, 8.0, precision=E.FP64, indicator=E.IND_FROZEN)
+    eng = E.Engine(cfg)
+    eng.set_state(d["rho"], d["ux"], d["uy"], d["T"], d["eps"])
+    eng.set_mask(np.ones(nc, np.uint8))
+    t0 = eng.conserved().sum(1).cpu().numpy()
+    eng.step(5)
+    t1 = eng.conserved().sum(1).cpu().numpy()
+    np.testing.assert_allclose(t1, t0, rtol=1e-13, atol=1e-12)
+
+
+# ------------------------------------------------------------ FP32 / BF16
+
+@pytest.mark.parametrize("gen,scheme,recon", FP64_CASES[1:3])
+def test_fully_kinetic_fp32_matches_oracle(gen, scheme, recon):
+    d = inputs.riemann4(**gen)
+    nc = d["nx"] * d["ny"]
+    p, eng, st = pair(d, scheme=scheme, recon=recon, precision=1, mask=np.ones(nc, np.uint8))
+    eng.step(5)
+    st.run(5, update_regime=False)
+    Ug = gpu_U(eng)
+    assert_U_close(Ug, st.U, 2e-5)
+    pg = np.stack([t.cpu().numpy() for t in eng.moments()])
+    po = st.prim()
+    rel = np.abs(pg - po) / np.abs(po).max(axis=1, keepdims=True)
+    assert rel.max() <= 2e-5
+
+
+def test_fp32_conservation_and_indicator_consistency():
+    """FP32 path with the regime update: the GPU mask equals the oracle
+    indicator applied to the GPU's own moments and L1 distances (bit-exact)."""
+    d = inputs.riemann4(nx=24, ny=20, nv=16, vmax=8.0, seed=12, log_eps_mean=-2.5)
+    cfg = E.make_config(24, 20, 16, 8.0, precision=E.FP32, indicator=E.IND_PLAIN, eta=5e-3)
+    eng = E.Engine(cfg)
+    eng.set_state(d["rho"], d["ux"], d["uy"], d["T"], d["eps"])
+    p = oracle.Problem(nx=24, ny=20, nv=16, vmax=8.0, eta=5e-3)
+    for step in range(5):
+        U_before = gpu_U(eng)
+        l1_before = eng.l1().cpu().numpy()
+        mask_before = eng.mask().cpu().numpy()
+        eng.step(1)
+        mask_after = eng.mask().cpu().numpy()
+        # the regime update of this step saw the state at its start
+        expect = oracle.indicator(p, oracle.primitives(U_before), d["eps"], l1_before, mask_before)
+        assert np.array_equal(mask_after, expect), step
+    assert eng.mask().cpu().numpy().sum() > 0
+
+
+def _U_of(prim):
+    rho, ux, uy, T = prim
+    return np.stack([rho, rho * ux, rho * uy, 0.5 * rho * (ux * ux + uy * uy) + rho * T])
