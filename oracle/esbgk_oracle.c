@@ -490,7 +490,12 @@ double orc_l1_to_maxwellian(const orc_cfg *c, const double *fc)
  * crit:CompEuler); kinetic -> fluid only when it does not and the L1 distance
  * is <= delta (Remark and eq. eqKintoFluid1):
  *   mask_new = crit_S || (mask_old && l1 > delta).
- * The operation order below is part of the contract with the GPU indicator. */
+ * The decision is evaluated without square roots, through the exact
+ * equivalences (ck eps/(tau sqrt T))^2 = (ck eps)^2/(tau^2 T) and
+ * |m| + sqrt(q) > eta <=> (eta - |m| < 0 or q > (eta - |m|)^2): it is then a
+ * composition of correctly rounded + - * / only.  The operation order below is
+ * part of the contract with the GPU indicator; the returned lambda (a report,
+ * not used in the decision) takes one square root. */
 void orc_indicator(const orc_cfg *c, const double *prim, const double *eps, const double *l1,
                    const uint8_t *mask_old, uint8_t *mask_new, double *lam_out)
 {
@@ -517,16 +522,18 @@ void orc_indicator(const orc_cfg *c, const double *prim, const double *eps, cons
         double Dxy = uxy + uyx;
         double Dyy = (uyy + uyy) - cD * div;
         double cv = eps[cell] / (c->tau * (1.0 - c->beta));
-        double kt = ck * eps[cell] / (c->tau * sqrt(T[cell]));
-        double kt2 = cS * (kt * kt);
+        double ke = ck * eps[cell];
+        double kt2 = cS * ((ke * ke) / ((c->tau * c->tau) * T[cell]));
         double a11 = -(cv * Dxx) - kt2 * (Tx * Tx);
         double a12 = -(cv * Dxy) - kt2 * (Tx * Ty);
         double a22 = -(cv * Dyy) - kt2 * (Ty * Ty);
         double m = (a11 + a22) / 2.0;
         double h = (a11 - a22) / 2.0;
-        double lam = fabs(m) + sqrt(h * h + a12 * a12);
-        if (lam_out) lam_out[cell] = lam;
-        int critS = lam > c->eta;
+        double q = h * h + a12 * a12;
+        if (lam_out) lam_out[cell] = fabs(m) + sqrt(q);
+        /* |m| + sqrt(q) > eta  <=>  eta - |m| < 0  or  q > (eta - |m|)^2 */
+        double dd = c->eta - fabs(m);
+        int critS = (dd < 0.0) || (q > dd * dd);
         int critL = l1[cell] > c->delta;
         mask_new[cell] = (uint8_t)(critS || (mask_old[cell] && critL));
     }
