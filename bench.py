@@ -49,6 +49,9 @@ def parse():
     ap.add_argument("--workload", default="riemann4", choices=sorted(WORKLOADS))
     ap.add_argument("--no-cpu-baseline", action="store_true")
     ap.add_argument("--cpu-steps", type=int, default=8)
+    ap.add_argument("--calibrate-copy", type=int, default=0, metavar="MIB",
+                    help="first run one plain device-to-device tensor copy of MIB MiB (a kernel of "
+                         "known traffic, to scale HBM byte counters)")
     return ap.parse_args()
 
 
@@ -90,6 +93,14 @@ def main():
 
     from paper_2512_03586_amd import esbgk as E
     from paper_2512_03586_amd import inputs
+
+    if args.calibrate_copy > 0:
+        n = args.calibrate_copy * (1 << 20) // 4
+        src = torch.ones(n, dtype=torch.float32, device="cuda")
+        dst = torch.empty_like(src)
+        dst.copy_(src)
+        torch.cuda.synchronize()
+        del src, dst
 
     wl = WORKLOADS[args.workload]
     prec = {"fp32": E.FP32, "bf16": E.BF16, "fp64": E.FP64}[args.precision]

@@ -1,14 +1,17 @@
 // device.h -- device-side building blocks of the MI355X kinetic IMEX engine.
 //
-// Work decomposition used by every phase-space kernel: one 64-lane wavefront
-// owns one cell's whole velocity block (nv*nv values, velocity-contiguous in
-// HBM).  Lane l owns "chunks" of 4 consecutive nodes k0 = 4*(l + 64*m),
-// m = 0..C-1, so a wavefront load instruction reads 64 x 16 B (FP32) of
-// contiguous memory.  nv is a multiple of 4, hence the 4 nodes of a chunk
-// share the same y-velocity.  Velocity reductions (moments, Gram sums) are
-// per-lane partial sums over the lane's chunks followed by a butterfly across
-// the wavefront; the butterfly only relies on commutativity of IEEE addition,
-// so every lane ends with the bit-identical total.
+// Work decomposition of every phase-space kernel: a group of L lanes
+// (L = 16, 32 or 64; a 16-lane group is one DPP row) owns one cell's whole
+// velocity block (nv*nv values, velocity-contiguous in HBM), so a 64-lane
+// wavefront works on 64/L cells at once.  Lane s of a group owns the chunks of
+// 4 consecutive nodes k0 = 4*(s + L*m), m = 0..C-1; nv is a multiple of 4, so
+// the 4 nodes of a chunk share one y-velocity.  A velocity reduction is a
+// per-lane partial sum followed by a butterfly inside the group made of DPP
+// lane permutations (plus one ds_swizzle / readlane step for 32- and 64-lane
+// groups); every butterfly step adds a pair of lanes symmetrically, and IEEE
+// addition is commutative, so every lane of a group ends with the
+// bit-identical total.  The per-cell FP64 algebra after a reduction therefore
+// runs once per wavefront for all of its cells.
 #pragma once
 
 #include <hip/hip_runtime.h>
@@ -50,8 +53,6 @@ template <> struct Storage<float> {
     }
 };
 
-__device__ inline float bf16_to_f32(uint32_t b) { return __uint_as_float(b << 16); }
-
 // round to nearest even (finite inputs)
 __device__ inline uint32_t f32_to_bf16(float f) {
     uint32_t u = __float_as_uint(f);
@@ -63,8 +64,8 @@ template <> struct Storage<bf16_t> {
     using T = float;
     __device__ static inline void load4(const bf16_t *p, size_t idx, float v[4]) {
         uint2 a = *reinterpret_cast<const uint2 *>(p + idx);
-        v[0] = bf16_to_f32(a.x & 0xFFFFu); v[1] = bf16_to_f32(a.x >> 16);
-        v[2] = bf16_to_f32(a.y & 0xFFFFu); v[3] = bf16_to_f32(a.y >> 16);
+        v[0] = __uint_as_float(a.x << 16); v[1] = __uint_as_float(a.x & 0xFFFF0000u);
+        v[2] = __uint_as_float(a.y << 16); v[3] = __uint_as_float(a.y & 0xFFFF0000u);
     }
     __device__ static inline void store4(bf16_t *p, size_t idx, const float v[4]) {
         uint2 a;
@@ -83,19 +84,62 @@ __device__ inline double fast_exp2(double x) { return exp2(x); }
 __device__ inline float minmod(float a, float b) { return __builtin_amdgcn_fmed3f(a, b, 0.0f); }
 __device__ inline double minmod(double a, double b) { return fmax(fmin(a, b), fmin(fmax(a, b), 0.0)); }
 
-// --------------------------------------------------------- wave reductions
+// ------------------------------------------------------ group reductions
 
-template <class T> __device__ inline T wave_sum(T v) {
-#pragma unroll
-    for (int off = 32; off >= 1; off >>= 1) v += __shfl_xor(v, off, 64);
+template <int CTRL> __device__ inline uint32_t dpp32(uint32_t v) {
+    return (uint32_t)__builtin_amdgcn_update_dpp(0, (int)v, CTRL, 0xF, 0xF, false);
+}
+__device__ inline uint32_t swz_xor16(uint32_t v) {
+    // ds_swizzle bit-mask mode inside 32-lane halves: and 0x1F, or 0, xor 0x10
+    return (uint32_t)__builtin_amdgcn_ds_swizzle((int)v, 0x401F);
+}
+
+// Value of the partner lane at butterfly step STEP:
+// 0: lane^1, 1: lane^2 (quad permutes), 2: half-row mirror, 3: row mirror,
+// 4: lane^16 (32-lane halves).
+template <int STEP> __device__ inline uint32_t partner32(uint32_t v) {
+    if constexpr (STEP == 0) return dpp32<0xB1>(v);   // quad_perm [1,0,3,2]
+    else if constexpr (STEP == 1) return dpp32<0x4E>(v);  // quad_perm [2,3,0,1]
+    else if constexpr (STEP == 2) return dpp32<0x141>(v); // row_half_mirror
+    else if constexpr (STEP == 3) return dpp32<0x140>(v); // row_mirror
+    else return swz_xor16(v);
+}
+
+template <int STEP> __device__ inline float partner(float v) {
+    return __uint_as_float(partner32<STEP>(__float_as_uint(v)));
+}
+template <int STEP> __device__ inline double partner(double v) {
+    uint64_t u = (uint64_t)__double_as_longlong(v);
+    uint32_t lo = partner32<STEP>((uint32_t)u), hi = partner32<STEP>((uint32_t)(u >> 32));
+    return __longlong_as_double((long long)(((uint64_t)hi << 32) | lo));
+}
+
+__device__ inline float readlane(float v, int l) {
+    return __int_as_float(__builtin_amdgcn_readlane(__float_as_int(v), l));
+}
+__device__ inline double readlane(double v, int l) {
+    uint64_t u = (uint64_t)__double_as_longlong(v);
+    uint32_t lo = (uint32_t)__builtin_amdgcn_readlane((int)(uint32_t)u, l);
+    uint32_t hi = (uint32_t)__builtin_amdgcn_readlane((int)(uint32_t)(u >> 32), l);
+    return __longlong_as_double((long long)(((uint64_t)hi << 32) | lo));
+}
+
+// Sum over the L lanes of a group; every lane of the group gets the same value.
+template <int L, class T> __device__ inline T group_sum(T v) {
+    v += partner<0>(v);
+    v += partner<1>(v);
+    v += partner<2>(v);
+    v += partner<3>(v);
+    if constexpr (L >= 32) v += partner<4>(v);
+    if constexpr (L == 64) v = readlane(v, 0) + readlane(v, 32);
     return v;
 }
 
-// Compensated (hi, lo) accumulator in the arithmetic type: TwoSum keeps the
-// exact rounding error of every addition in lo.
+// Compensated (hi, lo) pair: TwoSum keeps the exact rounding error of every
+// addition in lo.  merge() is symmetric in its operands (the TwoSum error term
+// is exact), so a butterfly of merges leaves identical pairs in all lanes.
 template <class T> struct Comp {
-    T hi, lo;
-    __device__ inline Comp() : hi(0), lo(0) {}
+    T hi = 0, lo = 0;
     __device__ inline void add(T x) {
         T s = hi + x;
         T bb = s - hi;
@@ -113,14 +157,19 @@ template <class T> struct Comp {
     __device__ inline double value() const { return (double)hi + (double)lo; }
 };
 
-template <class T> __device__ inline double wave_sum_comp(Comp<T> c) {
-#pragma unroll
-    for (int off = 32; off >= 1; off >>= 1) {
-        T ohi = __shfl_xor(c.hi, off, 64);
-        T olo = __shfl_xor(c.lo, off, 64);
-        // merge symmetrically: TwoSum's error term is exact, so (a,b) and (b,a)
-        // give identical results in both lanes of a pair
-        c.merge(ohi, olo);
+template <int L, class T> __device__ inline double group_sum_comp(Comp<T> c) {
+    c.merge(partner<0>(c.hi), partner<0>(c.lo));
+    c.merge(partner<1>(c.hi), partner<1>(c.lo));
+    c.merge(partner<2>(c.hi), partner<2>(c.lo));
+    c.merge(partner<3>(c.hi), partner<3>(c.lo));
+    if constexpr (L >= 32) c.merge(partner<4>(c.hi), partner<4>(c.lo));
+    if constexpr (L == 64) {
+        T h0 = readlane(c.hi, 0), l0 = readlane(c.lo, 0);
+        T h1 = readlane(c.hi, 32), l1 = readlane(c.lo, 32);
+        Comp<T> r;
+        r.hi = h0; r.lo = l0;
+        r.merge(h1, l1);
+        return r.value();
     }
     return c.value();
 }
@@ -134,36 +183,34 @@ struct Geom {
     int recon, correction;
 };
 
-// Chunk m of lane l: first node index, and whether it exists.
-__device__ inline int chunk_node(int lane, int m) { return 4 * (lane + 64 * m); }
-
 // ------------------------------------------ per-cell Gaussian parameters
 //
 // A sampled Gaussian with the conservation correction is stored per cell as
 // 16 doubles so that later kernels can re-evaluate it at any node without
 // touching the velocity block:
-//   Ghat(v) = exp2(l2p + qxx xi_x^2 + qxy xi_x xi_y + qyy xi_y^2) * (c . psi),
-//   xi = v - u, psi = (1, a, b, a^2, a b, b^2), (a, b) = xi / sqrt(T).
-enum GP { GP_UX = 0, GP_UY, GP_QXX, GP_QXY, GP_QYY, GP_L2P, GP_IST, GP_C0, GP_C1, GP_C2,
+//   Ghat(v) = exp2(qxx xi_x^2 + qxy xi_x xi_y + qyy xi_y^2) * (c . psi),
+//   xi = v - u, psi = (1, a, b, a^2, a b, b^2), (a, b) = xi / sqrt(T),
+// where the Gaussian's prefactor rho / (2 pi sqrt(det Tt)) is folded into c.
+enum GP { GP_UX = 0, GP_UY, GP_QXX, GP_QXY, GP_QYY, GP_PREF, GP_IST, GP_C0, GP_C1, GP_C2,
           GP_C3, GP_C4, GP_C5, GP_RHO, GP_T, GP_PAD, GP_N };
 
-// Fill the exponent part of the parameters of the Gaussian with density rho,
-// mean u and covariance tensor Tt (Sec. 2: rho / sqrt(det(2 pi Tt)) *
-// exp(-xi^T Tt^{-1} xi / 2)), all in FP64.  Returns false if Tt is not SPD.
+// Exponent part of the Gaussian with density rho, mean u and covariance Tt
+// (Sec. 2: rho / sqrt(det(2 pi Tt)) exp(-xi^T Tt^{-1} xi / 2)), FP64.
+// c = pref * e0 (no correction yet).  Returns false if Tt is not SPD.
 __device__ inline bool gauss_params(double rho, double ux, double uy, double T, double txx,
                                     double txy, double tyy, double *gp) {
-    double det = txx * tyy - txy * txy;
-    bool ok = det > 0.0 && txx > 0.0 && rho > 0.0 && T > 0.0;
-    double idet = 1.0 / det;
-    double ixx = tyy * idet, ixy = -txy * idet, iyy = txx * idet;
+    const double det = txx * tyy - txy * txy;
+    const bool ok = det > 0.0 && txx > 0.0 && rho > 0.0 && T > 0.0;
+    const double idet = 1.0 / det;
     gp[GP_UX] = ux;
     gp[GP_UY] = uy;
-    gp[GP_QXX] = -0.5 * kLog2e * ixx;
-    gp[GP_QXY] = -kLog2e * ixy;
-    gp[GP_QYY] = -0.5 * kLog2e * iyy;
-    gp[GP_L2P] = log2(rho / (2.0 * kPi * sqrt(det)));
+    gp[GP_QXX] = (-0.5 * kLog2e) * (tyy * idet);
+    gp[GP_QXY] = kLog2e * (txy * idet);
+    gp[GP_QYY] = (-0.5 * kLog2e) * (txx * idet);
+    const double pref = rho / (2.0 * kPi * sqrt(det));
+    gp[GP_PREF] = pref;
     gp[GP_IST] = 1.0 / sqrt(T);
-    gp[GP_C0] = 1.0;
+    gp[GP_C0] = pref;
     gp[GP_C1] = gp[GP_C2] = gp[GP_C3] = gp[GP_C4] = gp[GP_C5] = 0.0;
     gp[GP_RHO] = rho;
     gp[GP_T] = T;
@@ -171,50 +218,48 @@ __device__ inline bool gauss_params(double rho, double ux, double uy, double T, 
     return ok;
 }
 
-// Unknowns of the conservation correction from the 15 discrete moments
-// S_pq = w sum Gtilde a^p b^q (p + q <= 4) of the sampled Gaussian: the Gram
-// matrix A_mn = w sum Gtilde psi_m psi_n and the target moments
-// t = (rho, 0, 0, rho txx/T, rho txy/T, rho tyy/T).  Writes c into gp[GP_C0..].
-// Solved in deviation form A dc = t - A e0 (c = e0 + dc) by Cholesky in FP64.
+// The conservation correction from the 15 discrete moments
+// S_pq = w sum exp2(Q) a^p b^q (p + q <= 4) of the unscaled sampled Gaussian:
+// Gram matrix A_mn = pref S(psi_m psi_n) of Gtilde = pref exp2(Q), targets
+// t = (rho, 0, 0, rho txx/T, rho txy/T, rho tyy/T); solve A c = t in deviation
+// form A dc = t - A e0 (c = e0 + dc) by Cholesky in FP64, then fold pref into
+// c (gp[GP_C0..GP_C5] = pref * c).  Monomial order of S:
+// 00, 10, 01, 20, 11, 02, 30, 21, 12, 03, 40, 31, 22, 13, 04.
 __device__ inline bool solve_correction(const double S[15], double rho, double T, double txx,
                                         double txy, double tyy, double *gp) {
-    // monomial index of a^p b^q in S: order (00,10,01,20,11,02,30,21,12,03,40,31,22,13,04)
     const int pp[6] = {0, 1, 0, 2, 1, 0}, qq[6] = {0, 0, 1, 0, 1, 2};
-    auto mon = [&](int p, int q) -> double {
-        int d = p + q;
-        int base = d * (d + 1) / 2;  // 0,1,3,6,10
-        return S[base + q];
-    };
+    const double pref = gp[GP_PREF];
     double A[6][6];
 #pragma unroll
     for (int m = 0; m < 6; ++m)
 #pragma unroll
-        for (int n = 0; n < 6; ++n) A[m][n] = mon(pp[m] + pp[n], qq[m] + qq[n]);
+        for (int n = 0; n <= m; ++n) {
+            const int p = pp[m] + pp[n], q = qq[m] + qq[n], d = p + q;
+            A[m][n] = pref * S[d * (d + 1) / 2 + q];
+        }
+    const double iT = 1.0 / T;
     double r[6];
-    double iT = 1.0 / T;
     r[0] = rho - A[0][0];
     r[1] = -A[1][0];
     r[2] = -A[2][0];
     r[3] = rho * txx * iT - A[3][0];
     r[4] = rho * txy * iT - A[4][0];
     r[5] = rho * tyy * iT - A[5][0];
-    // Cholesky A = L L^T (in place, lower triangle)
     bool ok = true;
+    double il[6];
 #pragma unroll
     for (int j = 0; j < 6; ++j) {
         double d = A[j][j];
 #pragma unroll
         for (int k = 0; k < j; ++k) d -= A[j][k] * A[j][k];
         ok = ok && d > 0.0;
-        double ljj = sqrt(d);
-        A[j][j] = ljj;
-        double il = 1.0 / ljj;
+        il[j] = 1.0 / sqrt(d);
 #pragma unroll
         for (int i = j + 1; i < 6; ++i) {
             double s = A[i][j];
 #pragma unroll
             for (int k = 0; k < j; ++k) s -= A[i][k] * A[j][k];
-            A[i][j] = s * il;
+            A[i][j] = s * il[j];
         }
     }
     double y[6];
@@ -223,7 +268,7 @@ __device__ inline bool solve_correction(const double S[15], double rho, double T
         double s = r[i];
 #pragma unroll
         for (int k = 0; k < i; ++k) s -= A[i][k] * y[k];
-        y[i] = s / A[i][i];
+        y[i] = s * il[i];
     }
     double x[6];
 #pragma unroll
@@ -231,39 +276,53 @@ __device__ inline bool solve_correction(const double S[15], double rho, double T
         double s = y[i];
 #pragma unroll
         for (int k = i + 1; k < 6; ++k) s -= A[k][i] * x[k];
-        x[i] = s / A[i][i];
+        x[i] = s * il[i];
     }
     if (ok) {
-        gp[GP_C0] = 1.0 + x[0];
-        gp[GP_C1] = x[1];
-        gp[GP_C2] = x[2];
-        gp[GP_C3] = x[3];
-        gp[GP_C4] = x[4];
-        gp[GP_C5] = x[5];
+        gp[GP_C0] = pref * (1.0 + x[0]);
+        gp[GP_C1] = pref * x[1];
+        gp[GP_C2] = pref * x[2];
+        gp[GP_C3] = pref * x[3];
+        gp[GP_C4] = pref * x[4];
+        gp[GP_C5] = pref * x[5];
     }
     return ok;
 }
 
-// Per-lane copy of a cell's Gaussian parameters in the arithmetic type.
+// Per-lane copy of a cell's Gaussian parameters in the arithmetic type, with
+// the chunk-invariant parts of the exponent and the polynomial hoisted.
 template <class T> struct GaussEval {
-    T ux, uy, qxx, qxy, qyy, l2p, ist, c0, c1, c2, c3, c4, c5;
+    T ux, uy, qxx, qxy, qyy, ist, c0, c1, c2, c3, c4, c5;
     __device__ inline void load(const double *gp) {
         ux = (T)gp[GP_UX]; uy = (T)gp[GP_UY];
         qxx = (T)gp[GP_QXX]; qxy = (T)gp[GP_QXY]; qyy = (T)gp[GP_QYY];
-        l2p = (T)gp[GP_L2P]; ist = (T)gp[GP_IST];
+        ist = (T)gp[GP_IST];
         c0 = (T)gp[GP_C0]; c1 = (T)gp[GP_C1]; c2 = (T)gp[GP_C2];
         c3 = (T)gp[GP_C3]; c4 = (T)gp[GP_C4]; c5 = (T)gp[GP_C5];
     }
-    // sampled Gaussian (no correction)
-    __device__ inline T tilde(T vx, T vy) const {
-        T ex = vx - ux, ey = vy - uy;
-        return fast_exp2(l2p + (qxx * ex + qxy * ey) * ex + qyy * ey * ey);
+};
+
+// Chunk-level constants of a Gaussian at y-velocity vy.
+template <class T> struct GaussRow {
+    T qy_lin, qy_const, p_lin, p_const;  // exponent = (qxx ex + qy_lin) ex + qy_const
+    __device__ inline void set(const GaussEval<T> &g, T vy) {
+        const T ey = vy - g.uy;
+        const T b = ey * g.ist;
+        qy_lin = g.qxy * ey;
+        qy_const = g.qyy * ey * ey;
+        p_lin = g.c1 + g.c4 * b;                   // poly = (c3 a + p_lin) a + p_const
+        p_const = g.c0 + (g.c2 + g.c5 * b) * b;
     }
-    __device__ inline T poly(T vx, T vy) const {
-        T a = (vx - ux) * ist, b = (vy - uy) * ist;
-        return c0 + (c1 + c3 * a + c4 * b) * a + (c2 + c5 * b) * b;
+    // unscaled sampled Gaussian exp2(Q) at x-velocity vx
+    __device__ inline T tilde(const GaussEval<T> &g, T vx) const {
+        const T ex = vx - g.ux;
+        return fast_exp2((g.qxx * ex + qy_lin) * ex + qy_const);
     }
-    __device__ inline T hat(T vx, T vy) const { return tilde(vx, vy) * poly(vx, vy); }
+    __device__ inline T hat(const GaussEval<T> &g, T vx) const {
+        const T ex = vx - g.ux;
+        const T a = ex * g.ist;
+        return fast_exp2((g.qxx * ex + qy_lin) * ex + qy_const) * ((g.c3 * a + p_lin) * a + p_const);
+    }
 };
 
 // error flag bits

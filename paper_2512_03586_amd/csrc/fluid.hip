@@ -125,7 +125,10 @@ __global__ void conserved_kernel(const double *rho, const double *ux, const doub
 // ------------------------------------------------------------- indicator
 
 // Regime indicator of Sec. 3.1.2 at one cell.  The operation order matches the
-// documented contract (no contraction: explicit round-to-nearest intrinsics).
+// documented contract (no contraction, correctly rounded + - * / only: the
+// criterion lambda > eta is decided through the square-root-free equivalent
+// eta - |m| < 0 or q > (eta - |m|)^2, and (ck eps/(tau sqrt T))^2 is formed as
+// (ck eps)^2 / (tau^2 T)).
 __device__ inline uint8_t indicator_cell(const IndicatorArgs &a, int cell, double *lam_out) {
     const size_t n = (size_t)a.nc;
     const int nx = a.nx, ny = a.ny;
@@ -146,16 +149,18 @@ __device__ inline uint8_t indicator_cell(const IndicatorArgs &a, int cell, doubl
     const double Dyy = __dsub_rn(__dadd_rn(uyy, uyy), __dmul_rn(a.cD, div));
     const double e = a.eps[cell];
     const double cv = __ddiv_rn(e, __dmul_rn(a.tau, a.omb));
-    const double kt = __ddiv_rn(__dmul_rn(a.ck, e), __dmul_rn(a.tau, __dsqrt_rn(T[cell])));
-    const double kt2 = __dmul_rn(a.cS, __dmul_rn(kt, kt));
+    const double ke = __dmul_rn(a.ck, e);
+    const double kt2 = __dmul_rn(a.cS, __ddiv_rn(__dmul_rn(ke, ke), __dmul_rn(__dmul_rn(a.tau, a.tau), T[cell])));
     const double a11 = __dsub_rn(-__dmul_rn(cv, Dxx), __dmul_rn(kt2, __dmul_rn(Tx, Tx)));
     const double a12 = __dsub_rn(-__dmul_rn(cv, Dxy), __dmul_rn(kt2, __dmul_rn(Tx, Ty)));
     const double a22 = __dsub_rn(-__dmul_rn(cv, Dyy), __dmul_rn(kt2, __dmul_rn(Ty, Ty)));
     const double m = __ddiv_rn(__dadd_rn(a11, a22), 2.0);
     const double h = __ddiv_rn(__dsub_rn(a11, a22), 2.0);
-    const double lam = __dadd_rn(fabs(m), __dsqrt_rn(__dadd_rn(__dmul_rn(h, h), __dmul_rn(a12, a12))));
-    if (lam_out) *lam_out = lam;
-    const bool critS = lam > a.eta;
+    const double q = __dadd_rn(__dmul_rn(h, h), __dmul_rn(a12, a12));
+    if (lam_out) *lam_out = fabs(m) + sqrt(q);  // report only
+    // |m| + sqrt(q) > eta  <=>  eta - |m| < 0  or  q > (eta - |m|)^2: no square root decides
+    const double dd = __dsub_rn(a.eta, fabs(m));
+    const bool critS = (dd < 0.0) || (q > __dmul_rn(dd, dd));
     const bool critL = a.l1[cell] > a.delta;
     return (uint8_t)(critS || (a.mask_old[cell] && critL));
 }

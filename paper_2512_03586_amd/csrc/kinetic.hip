@@ -1,21 +1,27 @@
 // kinetic.hip -- phase-space kernels of the kinetic IMEX stage (ES-BGK, 2D2V).
 //
-// stage_kernel fuses, for one kinetic cell per wavefront:
+// stage_kernel fuses, for every kinetic cell (one L-lane group per cell):
 //   transport L(f^(j)) of earlier stages at every node (upwind or minmod-limited
 //     upwind flux, Sec. 3.2), read straight from the velocity-contiguous f arrays;
 //   the explicit stage sum f* = f^n - dt sum_j At_ij L(f^(j))
 //     + dt sum_j A_ij (tau/eps)(Ghat_j - f^(j)) (eq. RKEI1), where Ghat_j is
 //     re-evaluated from the per-cell parameters stage j stored;
-//   the velocity moments of f* (rho, u, T, Theta; H3 and Sec. 2), compensated;
+//   the velocity moments of f* (rho, u, T, Theta; H3 and Sec. 2), with
+//     compensated FP32 sums;
 //   the FP64 closed form of the implicit relaxation,
 //     Theta = (Theta* + lam (1-beta) T I) / (1 + lam (1-beta)),
 //     Tt = (1-beta) T I + beta Theta, lam = dt A_ii tau/eps,
-//     and the 6x6 discrete-conservation correction of the sampled Gaussian;
+//     and the FP64 6x6 discrete-conservation correction of the sampled Gaussian;
 //   f^(i) = (f* + lam Ghat) / (1 + lam), the single write of the stage.
-// With aii = 0 the same kernel is the final combination (eq. RKEI2): it writes
-// f^{n+1}, its moments U^{n+1} and the L1 distance to the Maxwellian used by the
-// next regime update (eq. eqKintoFluid1).
+// The FINAL variant is the final combination (eq. RKEI2): it writes f^{n+1},
+// its moments U^{n+1} and the L1 distance to the Maxwellian that the next
+// regime update reads (eq. eqKintoFluid1).
 #include "kernels.h"
+
+// waves per SIMD the stage kernels are compiled for (caps their VGPR budget)
+#ifndef ESBGK_STAGE_MIN_WAVES
+#define ESBGK_STAGE_MIN_WAVES 4
+#endif
 
 namespace esbgk {
 
@@ -26,8 +32,8 @@ struct Nbr {
 };
 
 __device__ inline Nbr neighbours(int cell, const Geom &g) {
-    int i = cell % g.nx, j = cell / g.nx;
-    size_t n2 = (size_t)g.nv2;
+    const int i = cell % g.nx, j = cell / g.nx;
+    const size_t n2 = (size_t)g.nv2;
     Nbr b;
     b.c = (size_t)cell * n2;
     b.xm1 = ((size_t)j * g.nx + wrapi(i - 1, g.nx)) * n2;
@@ -42,293 +48,481 @@ __device__ inline Nbr neighbours(int cell, const Geom &g) {
 }
 
 // Upwind-mirrored limited difference: with g_{-2}, g_{-1}, g_0, g_1 the values
-// ordered along the flow, |v| (F_{+1/2} - F_{-1/2}) / h equals
-//   |v| (q + (minmod(q, r) - minmod(p, q)) / 2) / h,
+// ordered along the flow, (F_{+1/2} - F_{-1/2}) / |v| equals
+//   q + (minmod(q, r) - minmod(p, q)) / 2,
 //   p = g_{-1} - g_{-2}, q = g_0 - g_{-1}, r = g_1 - g_0.
 template <class T> __device__ inline T limited_diff(T far, T up, T c, T dn) {
-    T p = up - far, q = c - up, r = dn - c;
+    const T p = up - far, q = c - up, r = dn - c;
     return q + (T)0.5 * (minmod(q, r) - minmod(p, q));
 }
 
-// L(f) at the 4 nodes of one chunk.
+// Velocity bookkeeping of one chunk: first node k0, x-velocities of its 4
+// nodes, its y-velocity.
+template <class T> struct Chunk {
+    int k0;
+    bool active;
+    T vx[4], vy;
+};
+
+// |v_x| (F_{i+1/2} - F_{i-1/2}) / dx + |v_y| (G_{j+1/2} - G_{j-1/2}) / dy at the
+// 4 nodes of a chunk (the transport operator L), and the cell's own values fc.
 template <class S>
-__device__ inline void transport4(const S *f, const Nbr &nb, int k0, const typename Storage<S>::T vx[4],
-                                  typename Storage<S>::T vy, typename Storage<S>::T idx,
-                                  typename Storage<S>::T idy, int recon, typename Storage<S>::T out[4]) {
+__device__ inline void transport4(const S *f, const Nbr &nb, const Chunk<typename Storage<S>::T> &ch,
+                                  typename Storage<S>::T idx, typename Storage<S>::T idy, int recon,
+                                  typename Storage<S>::T fc[4], typename Storage<S>::T out[4]) {
     using T = typename Storage<S>::T;
-    T fc[4], xm1[4], xp1[4];
+    const int k0 = ch.k0;
     Storage<S>::load4(f, nb.c + k0, fc);
-    const bool anypos = vx[3] > (T)0, anyneg = vx[0] < (T)0;
-    const bool ypos = vy > (T)0;
-    const size_t yup = ypos ? nb.ym1 : nb.yp1;
-    const size_t ydn = ypos ? nb.yp1 : nb.ym1;
-    const size_t yfar = ypos ? nb.ym2 : nb.yp2;
-    const T avy = ypos ? vy : -vy;
+    // y: one velocity per chunk, pick the upwind / downwind / far neighbours
+    const bool ypos = ch.vy > (T)0;
+    const T avy = (ypos ? ch.vy : -ch.vy) * idy;
     T yu[4];
-    Storage<S>::load4(f, yup + k0, yu);
-#pragma unroll
-    for (int e = 0; e < 4; ++e) { xm1[e] = 0; xp1[e] = 0; }
+    Storage<S>::load4(f, (ypos ? nb.ym1 : nb.yp1) + k0, yu);
+    T Ly[4];
     if (recon == 0) {
-        if (anypos) Storage<S>::load4(f, nb.xm1 + k0, xm1);
-        if (anyneg) Storage<S>::load4(f, nb.xp1 + k0, xp1);
 #pragma unroll
-        for (int e = 0; e < 4; ++e) {
-            const bool pos = vx[e] > (T)0;
-            T up = pos ? xm1[e] : xp1[e];
-            T avx = pos ? vx[e] : -vx[e];
-            out[e] = avx * (fc[e] - up) * idx + avy * (fc[e] - yu[e]) * idy;
+        for (int e = 0; e < 4; ++e) Ly[e] = avy * (fc[e] - yu[e]);
+    } else {
+        T yd[4], yf[4];
+        Storage<S>::load4(f, (ypos ? nb.yp1 : nb.ym1) + k0, yd);
+        Storage<S>::load4(f, (ypos ? nb.ym2 : nb.yp2) + k0, yf);
+#pragma unroll
+        for (int e = 0; e < 4; ++e) Ly[e] = avy * limited_diff(yf[e], yu[e], fc[e], yd[e]);
+    }
+    // x: the 4 nodes of a chunk share the sign of v_x unless the chunk straddles 0
+    const bool anypos = ch.vx[3] > (T)0, anyneg = ch.vx[0] < (T)0;
+    if (!(anypos && anyneg)) {
+        const bool pos = anypos;
+        T xu[4];
+        Storage<S>::load4(f, (pos ? nb.xm1 : nb.xp1) + k0, xu);
+        if (recon == 0) {
+#pragma unroll
+            for (int e = 0; e < 4; ++e) {
+                const T avx = (pos ? ch.vx[e] : -ch.vx[e]) * idx;
+                out[e] = avx * (fc[e] - xu[e]) + Ly[e];
+            }
+        } else {
+            T xd[4], xf[4];
+            Storage<S>::load4(f, (pos ? nb.xp1 : nb.xm1) + k0, xd);
+            Storage<S>::load4(f, (pos ? nb.xm2 : nb.xp2) + k0, xf);
+#pragma unroll
+            for (int e = 0; e < 4; ++e) {
+                const T avx = (pos ? ch.vx[e] : -ch.vx[e]) * idx;
+                out[e] = avx * limited_diff(xf[e], xu[e], fc[e], xd[e]) + Ly[e];
+            }
         }
     } else {
-        T xm2[4], xp2[4], yd[4], yf[4];
-#pragma unroll
-        for (int e = 0; e < 4; ++e) { xm2[e] = 0; xp2[e] = 0; }
+        // straddling chunk (nv not a multiple of 8): per-node selection
+        T xm1[4], xp1[4], xm2[4], xp2[4];
         Storage<S>::load4(f, nb.xm1 + k0, xm1);
         Storage<S>::load4(f, nb.xp1 + k0, xp1);
-        if (anypos) Storage<S>::load4(f, nb.xm2 + k0, xm2);
-        if (anyneg) Storage<S>::load4(f, nb.xp2 + k0, xp2);
-        Storage<S>::load4(f, ydn + k0, yd);
-        Storage<S>::load4(f, yfar + k0, yf);
+        Storage<S>::load4(f, nb.xm2 + k0, xm2);
+        Storage<S>::load4(f, nb.xp2 + k0, xp2);
 #pragma unroll
         for (int e = 0; e < 4; ++e) {
-            const bool pos = vx[e] > (T)0;
-            T far = pos ? xm2[e] : xp2[e];
-            T up = pos ? xm1[e] : xp1[e];
-            T dn = pos ? xp1[e] : xm1[e];
-            T avx = pos ? vx[e] : -vx[e];
-            out[e] = avx * limited_diff(far, up, fc[e], dn) * idx +
-                     avy * limited_diff(yf[e], yu[e], fc[e], yd[e]) * idy;
+            const bool pos = ch.vx[e] > (T)0;
+            const T avx = (pos ? ch.vx[e] : -ch.vx[e]) * idx;
+            const T up = pos ? xm1[e] : xp1[e];
+            if (recon == 0) {
+                out[e] = avx * (fc[e] - up) + Ly[e];
+            } else {
+                const T far = pos ? xm2[e] : xp2[e];
+                const T dn = pos ? xp1[e] : xm1[e];
+                out[e] = avx * limited_diff(far, up, fc[e], dn) + Ly[e];
+            }
         }
     }
 }
 
-__device__ inline void raise_err(int *err, int bits) {
-    if (bits && (threadIdx.x & 63) == 0) atomicOr(err, bits);
+__device__ inline void raise_err(int *err, int bits, bool leader) {
+    if (bits && leader) atomicOr(err, bits);
 }
 
 // XCD-aware work assignment: blocks are dealt to the 8 XCDs round-robin, so
-// block b runs on XCD b % 8; give each XCD a contiguous range of the cell list
-// (contiguous cells share halo data in that XCD's L2).
-__device__ inline int logical_item(int count, int waves_per_block) {
-    int nblk = (count + waves_per_block - 1) / waves_per_block;
-    int per = (nblk + 7) / 8;
-    int b = blockIdx.x;
-    int xcd = b & 7, r = b >> 3;
+// block b runs on XCD b % 8; each XCD gets a contiguous range of the cell list
+// (contiguous list entries are spatially close cells that share halo data in
+// that XCD's L2).  Returns the first list item of this block or -1.
+__device__ inline int block_first_item(int count, int cells_per_block) {
+    const int nblk = (count + cells_per_block - 1) / cells_per_block;
+    const int per = (nblk + 7) / 8;
+    const int b = blockIdx.x;
+    const int xcd = b & 7, r = b >> 3;
     if (r >= per) return -1;
-    int lb = xcd * per + r;
-    int item = lb * waves_per_block + (threadIdx.x >> 6);
-    return item < count ? item : -1;
+    const int first = (xcd * per + r) * cells_per_block;
+    return first < count ? first : -1;
 }
 
-template <class S, int C>
-__global__ __launch_bounds__(256) void stage_kernel(StageArgs<S> a) {
-    using T = typename Storage<S>::T;
-    const Geom &g = a.g;
-    const int count = *a.count;
-    const int item = logical_item(count, 4);
-    if (item < 0) return;
-    const int cell = a.list[item];
-    const int lane = threadIdx.x & 63;
-    const Nbr nb = neighbours(cell, g);
-    const T dv = (T)g.dv, vmax = (T)g.vmax;
-    const T idx = (T)(1.0 / g.dx), idy = (T)(1.0 / g.dy);
-    const double te = g.tau / a.eps[cell];
-    const T dt = (T)g.dt;
+// Cell of this lane's group (-1 if the whole wavefront has no work).  Groups
+// past the end of the list work on the last listed cell and store nothing, so
+// that every lane takes part in the group-wide reductions.
+struct GroupCell {
+    int cell;
+    bool valid;
+};
 
-    GaussEval<T> ge[2];
-    for (int q = 0; q < a.nq; ++q) ge[q].load(a.pq[q] + (size_t)cell * GP_N);
+template <int L> __device__ inline GroupCell group_cell(const int *list, int count) {
+    constexpr int G = 64 / L;
+    GroupCell gc{-1, false};
+    const int first = block_first_item(count, 4 * G);
+    if (first < 0) return gc;
+    const int wave_first = first + (int)(threadIdx.x >> 6) * G;
+    if (wave_first >= count) return gc;
+    int item = wave_first + (int)((threadIdx.x & 63) / L);
+    gc.valid = item < count;
+    if (!gc.valid) item = count - 1;
+    gc.cell = list[item];
+    return gc;
+}
 
-    T fs[C][4];
-    T vx0[C], vyc[C];
-    Comp<T> s0, sx, sy;
+// Chunk m of sub-lane s.
+template <class T, int L>
+__device__ inline Chunk<T> chunk_of(int s, int m, const Geom &g) {
+    Chunk<T> ch;
+    const int c = s + L * m;
+    ch.k0 = 4 * c;
+    ch.active = ch.k0 < g.nv2;
+    const int nq4 = g.nv >> 2;
+    const int ia = 4 * (c % nq4), ib = c / nq4;
+    const T dv = (T)g.dv, v0 = (T)(-g.vmax + 0.5 * g.dv);
+    ch.vy = v0 + (T)ib * dv;
+#pragma unroll
+    for (int e = 0; e < 4; ++e) ch.vx[e] = v0 + (T)(ia + e) * dv;
+    return ch;
+}
+
+// The 15 unscaled discrete moments S_pq = sum exp2(Q) a^p b^q (p + q <= 4) of a
+// sampled Gaussian over the group's nodes (weight and prefactor are applied by
+// the caller); the six of order <= 2 are compensated.  Order of S:
+// 00 10 01 20 11 02 30 21 12 03 40 31 22 13 04.
+template <class T, int L, int C>
+__device__ inline void gram_sums(const GaussEval<T> &ge, int s, const Geom &g, double S[15]) {
+    Comp<T> lowc[6];
+    T low[6] = {0, 0, 0, 0, 0, 0};
+    T high[9] = {0, 0, 0, 0, 0, 0, 0, 0, 0};
 #pragma unroll
     for (int m = 0; m < C; ++m) {
-        const int k0 = chunk_node(lane, m);
-        const int ia = k0 % g.nv, ib = k0 / g.nv;
-        vx0[m] = -vmax + ((T)ia + (T)0.5) * dv;
-        vyc[m] = -vmax + ((T)ib + (T)0.5) * dv;
+        const Chunk<T> ch = chunk_of<T, L>(s, m, g);
+        if (ch.active) {
+            GaussRow<T> gr;
+            gr.set(ge, ch.vy);
+            const T b = (ch.vy - ge.uy) * ge.ist;
+            T p[5] = {0, 0, 0, 0, 0};
 #pragma unroll
-        for (int e = 0; e < 4; ++e) fs[m][e] = 0;
-        if (k0 < g.nv2) {
-            T vx[4];
+            for (int e = 0; e < 4; ++e) {
+                const T G = gr.tilde(ge, ch.vx[e]);
+                const T a = (ch.vx[e] - ge.ux) * ge.ist;
+                const T Ga = G * a, Ga2 = Ga * a, Ga3 = Ga2 * a;
+                p[0] += G; p[1] += Ga; p[2] += Ga2; p[3] += Ga3; p[4] += Ga3 * a;
+            }
+            const T b2 = b * b, b3 = b2 * b, b4 = b2 * b2;
+            low[0] += p[0]; low[1] += p[1]; low[2] += b * p[0];
+            low[3] += p[2]; low[4] += b * p[1]; low[5] += b2 * p[0];
+            high[0] += p[3]; high[1] += b * p[2]; high[2] += b2 * p[1]; high[3] += b3 * p[0];
+            high[4] += p[4]; high[5] += b * p[3]; high[6] += b2 * p[2]; high[7] += b3 * p[1];
+            high[8] += b4 * p[0];
+        }
+        if ((m & 3) == 3 || m == C - 1) {
 #pragma unroll
-            for (int e = 0; e < 4; ++e) vx[e] = vx0[m] + (T)e * dv;
-            T base[4], accL[4] = {0, 0, 0, 0}, accS[4] = {0, 0, 0, 0};
-            Storage<S>::load4(a.fn, nb.c + k0, base);
-            for (int l = 0; l < a.nl; ++l) {
-                T L[4];
-                transport4<S>(a.fl[l], nb, k0, vx, vyc[m], idx, idy, g.recon, L);
+            for (int q = 0; q < 6; ++q) { lowc[q].add(low[q]); low[q] = 0; }
+        }
+    }
+#pragma unroll
+    for (int q = 0; q < 6; ++q) S[q] = group_sum_comp<L>(lowc[q]);
+#pragma unroll
+    for (int q = 0; q < 9; ++q) S[6 + q] = (double)group_sum<L>(high[q]);
+}
+
+// Group-wide moments of the values v: compensated sums of f, v f and the raw
+// second moments, centred in FP64.  out = {rho, ux, uy, T, Thxx, Thxy, Thyy}.
+template <class T, int L, int C>
+__device__ inline void group_moments(const T v[C][4], int s, const Geom &g, double out[7]) {
+    Comp<T> cs[6];
+    T part[6] = {0, 0, 0, 0, 0, 0};
+#pragma unroll
+    for (int m = 0; m < C; ++m) {
+        const Chunk<T> ch = chunk_of<T, L>(s, m, g);
+        if (ch.active) {
+            const T c0 = (v[m][0] + v[m][1]) + (v[m][2] + v[m][3]);
+            const T cx = (ch.vx[0] * v[m][0] + ch.vx[1] * v[m][1]) + (ch.vx[2] * v[m][2] + ch.vx[3] * v[m][3]);
+            const T cxx = (ch.vx[0] * ch.vx[0] * v[m][0] + ch.vx[1] * ch.vx[1] * v[m][1]) +
+                          (ch.vx[2] * ch.vx[2] * v[m][2] + ch.vx[3] * ch.vx[3] * v[m][3]);
+            part[0] += c0;
+            part[1] += cx;
+            part[2] += ch.vy * c0;
+            part[3] += cxx;
+            part[4] += ch.vy * cx;
+            part[5] += ch.vy * ch.vy * c0;
+        }
+        if ((m & 3) == 3 || m == C - 1) {
+#pragma unroll
+            for (int q = 0; q < 6; ++q) { cs[q].add(part[q]); part[q] = 0; }
+        }
+    }
+    double M[6];
+#pragma unroll
+    for (int q = 0; q < 6; ++q) M[q] = g.w * group_sum_comp<L>(cs[q]);
+    const double rho = M[0];
+    const double irho = 1.0 / rho;
+    const double ux = M[1] * irho, uy = M[2] * irho;
+    const double pxx = M[3] - rho * ux * ux, pxy = M[4] - rho * ux * uy, pyy = M[5] - rho * uy * uy;
+    out[0] = rho;
+    out[1] = ux;
+    out[2] = uy;
+    out[3] = 0.5 * (pxx + pyy) * irho;
+    out[4] = pxx * irho;
+    out[5] = pxy * irho;
+    out[6] = pyy * irho;
+}
+
+// L1 distance (eq. eqKintoFluid1) of the values v to the sampled Maxwellian
+// with moments (rho, u, T), over the group's nodes.
+template <class T, int L, int C>
+__device__ inline double group_l1(const T v[C][4], int s, const Geom &g, double rho, double ux, double uy,
+                                  double Tm) {
+    const T pref = (T)(rho / (2.0 * kPi * Tm));
+    const T qm = (T)(-0.5 * kLog2e / Tm);
+    const T uxt = (T)ux, uyt = (T)uy;
+    T l1 = 0;
+#pragma unroll
+    for (int m = 0; m < C; ++m) {
+        const Chunk<T> ch = chunk_of<T, L>(s, m, g);
+        if (ch.active) {
+            const T ey = ch.vy - uyt;
+            const T qy = qm * ey * ey;
+#pragma unroll
+            for (int e = 0; e < 4; ++e) {
+                const T ex = ch.vx[e] - uxt;
+                l1 += fabs(v[m][e] - pref * fast_exp2(qm * ex * ex + qy));
+            }
+        }
+    }
+    return g.w * (double)group_sum<L>(l1);
+}
+
+// FP64 Gaussian parameters of the relaxed state and its conservation
+// correction; returns the error bits.
+template <class T, int L, int C>
+__device__ inline int relaxed_gaussian(const double mo[7], double lam, int s, const Geom &g, double gp[GP_N]) {
+    const double beta = g.beta;
+    const double rho = mo[0], ux = mo[1], uy = mo[2], Tm = mo[3];
+    const double k = lam * (1.0 - beta);
+    const double ik = 1.0 / (1.0 + k);
+    const double thxx = (mo[4] + k * Tm) * ik;
+    const double thxy = mo[5] * ik;
+    const double thyy = (mo[6] + k * Tm) * ik;
+    const double txx = (1.0 - beta) * Tm + beta * thxx;
+    const double txy = beta * thxy;
+    const double tyy = (1.0 - beta) * Tm + beta * thyy;
+    int err = 0;
+    if (!gauss_params(rho, ux, uy, Tm, txx, txy, tyy, gp)) err |= ERR_SPD;
+    if (g.correction) {
+        GaussEval<T> ge;
+        ge.load(gp);
+        double S[15];
+        gram_sums<T, L, C>(ge, s, g, S);
+#pragma unroll
+        for (int q = 0; q < 15; ++q) S[q] *= g.w;
+        if (!solve_correction(S, rho, Tm, txx, txy, tyy, gp)) err |= ERR_SPD;
+    }
+    return err;
+}
+
+// Moment partial sums of one chunk of values v into part[6] (sum f, vx f,
+// vy f, vx^2 f, vx vy f, vy^2 f), folded into the compensated lane sums every
+// 4 chunks.
+template <class T> struct MomentAcc {
+    Comp<T> cs[6];
+    T part[6] = {0, 0, 0, 0, 0, 0};
+    __device__ inline void add(const Chunk<T> &ch, const T v[4]) {
+        const T c0 = (v[0] + v[1]) + (v[2] + v[3]);
+        const T cx = (ch.vx[0] * v[0] + ch.vx[1] * v[1]) + (ch.vx[2] * v[2] + ch.vx[3] * v[3]);
+        const T cxx = (ch.vx[0] * ch.vx[0] * v[0] + ch.vx[1] * ch.vx[1] * v[1]) +
+                      (ch.vx[2] * ch.vx[2] * v[2] + ch.vx[3] * ch.vx[3] * v[3]);
+        part[0] += c0;
+        part[1] += cx;
+        part[2] += ch.vy * c0;
+        part[3] += cxx;
+        part[4] += ch.vy * cx;
+        part[5] += ch.vy * ch.vy * c0;
+    }
+    __device__ inline void fold() {
+#pragma unroll
+        for (int q = 0; q < 6; ++q) { cs[q].add(part[q]); part[q] = 0; }
+    }
+    // {rho, ux, uy, T, Thxx, Thxy, Thyy} of the group
+    template <int L> __device__ inline void finish(double w, double out[7]) {
+        fold();
+        double M[6];
+#pragma unroll
+        for (int q = 0; q < 6; ++q) M[q] = w * group_sum_comp<L>(cs[q]);
+        const double rho = M[0];
+        const double irho = 1.0 / rho;
+        const double ux = M[1] * irho, uy = M[2] * irho;
+        const double pxx = M[3] - rho * ux * ux, pxy = M[4] - rho * ux * uy, pyy = M[5] - rho * uy * uy;
+        out[0] = rho;
+        out[1] = ux;
+        out[2] = uy;
+        out[3] = 0.5 * (pxx + pyy) * irho;
+        out[4] = pxx * irho;
+        out[5] = pxy * irho;
+        out[6] = pyy * irho;
+    }
+};
+
+// Per-lane staging of the explicit stage values f* in LDS between the
+// explicit pass and the relaxation: each lane writes and reads back only its
+// own 16-byte (FP32) slots, so no barrier is needed.
+template <class T, int C> struct StageLds {
+    T v[4][C][64][4];  // [wave in block][chunk][lane][node]
+};
+
+template <class S, int L, int C, int NL, int NQ, bool FINAL>
+__global__ __launch_bounds__(256, ESBGK_STAGE_MIN_WAVES) void stage_kernel(StageArgs<S> a) {
+    using T = typename Storage<S>::T;
+    __shared__ StageLds<T, C> lds;
+    const Geom &g = a.g;
+    const GroupCell gc = group_cell<L>(a.list, *a.count);
+    if (gc.cell < 0) return;
+    const int cell = gc.cell;
+    const int lane = (int)(threadIdx.x & 63), wave = (int)(threadIdx.x >> 6);
+    const int s = lane & (L - 1);
+    const bool leader = gc.valid && s == 0;
+    const Nbr nb = neighbours(cell, g);
+    const T idx = (T)(1.0 / g.dx), idy = (T)(1.0 / g.dy);
+    const double te = g.tau / a.eps[cell];
+    const T dt = (T)g.dt, dtte = (T)(g.dt * te);
+
+    GaussEval<T> gq[NQ > 0 ? NQ : 1];
+#pragma unroll
+    for (int q = 0; q < NQ; ++q) gq[q].load(a.pq[q] + (size_t)cell * GP_N);
+
+    // ---- explicit part of the stage, moments on the fly
+    MomentAcc<T> macc;
+#pragma unroll
+    for (int m = 0; m < C; ++m) {
+        const Chunk<T> ch = chunk_of<T, L>(s, m, g);
+        if (ch.active) {
+            T base[4], acc[4] = {0, 0, 0, 0}, fs[4];
+#pragma unroll
+            for (int l = 0; l < NL; ++l) {
+                T fc[4], Lt[4];
+                transport4<S>(a.fl[l], nb, ch, idx, idy, g.recon, fc, Lt);
                 const T cl = (T)a.cl[l];
 #pragma unroll
-                for (int e = 0; e < 4; ++e) accL[e] += cl * L[e];
-            }
-            for (int q = 0; q < a.nq; ++q) {
-                T fj[4];
-                Storage<S>::load4(a.fq[q], nb.c + k0, fj);
-                const T cq = (T)a.cq[q];
+                for (int e = 0; e < 4; ++e) acc[e] += cl * Lt[e];
+                if (l == 0 && !FINAL) {
 #pragma unroll
-                for (int e = 0; e < 4; ++e) accS[e] += cq * (ge[q].hat(vx[e], vyc[m]) - fj[e]);
-            }
-            const T dtte = (T)(g.dt * te);
-#pragma unroll
-            for (int e = 0; e < 4; ++e) fs[m][e] = base[e] - dt * accL[e] + dtte * accS[e];
-            T c0 = (fs[m][0] + fs[m][1]) + (fs[m][2] + fs[m][3]);
-            T cx = (vx[0] * fs[m][0] + vx[1] * fs[m][1]) + (vx[2] * fs[m][2] + vx[3] * fs[m][3]);
-            s0.add(c0);
-            sx.add(cx);
-            sy.add(vyc[m] * c0);
-        }
-    }
-    // ---- first moments (compensated in the arithmetic type)
-    const double w = g.w;
-    const double rho = w * wave_sum_comp(s0);
-    const double ux = w * wave_sum_comp(sx) / rho;
-    const double uy = w * wave_sum_comp(sy) / rho;
-    // ---- centred second moments
-    Comp<T> pxx, pxy, pyy;
-    {
-        const T uxt = (T)ux, uyt = (T)uy;
-#pragma unroll
-        for (int m = 0; m < C; ++m) {
-            if (chunk_node(lane, m) < g.nv2) {
-                T ey = vyc[m] - uyt;
-                T a0 = 0, a1 = 0, a2 = 0;
-#pragma unroll
-                for (int e = 0; e < 4; ++e) {
-                    T ex = vx0[m] + (T)e * dv - uxt;
-                    a0 += ex * ex * fs[m][e];
-                    a1 += ex * fs[m][e];
-                    a2 += fs[m][e];
+                    for (int e = 0; e < 4; ++e) base[e] = fc[e];  // the stages transport f^n first
                 }
-                pxx.add(a0);
-                pxy.add(ey * a1);
-                pyy.add(ey * ey * a2);
             }
+            if (FINAL) Storage<S>::load4(a.fn, nb.c + ch.k0, base);
+#pragma unroll
+            for (int e = 0; e < 4; ++e) fs[e] = base[e] - dt * acc[e];
+#pragma unroll
+            for (int q = 0; q < NQ; ++q) {
+                T fj[4];
+                Storage<S>::load4(a.fq[q], nb.c + ch.k0, fj);
+                GaussRow<T> gr;
+                gr.set(gq[q], ch.vy);
+                const T cq = (T)a.cq[q] * dtte;
+#pragma unroll
+                for (int e = 0; e < 4; ++e) fs[e] += cq * (gr.hat(gq[q], ch.vx[e]) - fj[e]);
+            }
+            macc.add(ch, fs);
+#pragma unroll
+            for (int e = 0; e < 4; ++e) lds.v[wave][m][lane][e] = fs[e];
+            if (FINAL && gc.valid) Storage<S>::store4(a.fout, nb.c + ch.k0, fs);
         }
+        if ((m & 3) == 3) macc.fold();
     }
-    const double Pxx = w * wave_sum_comp(pxx), Pxy = w * wave_sum_comp(pxy), Pyy = w * wave_sum_comp(pyy);
-    const double Tm = (Pxx + Pyy) / (2.0 * rho);
+
+    // ---- moments of f*
+    double mo[7];
+    macc.template finish<L>(g.w, mo);
+    const double rho = mo[0], ux = mo[1], uy = mo[2], Tm = mo[3];
     int errbits = 0;
     if (!(rho > 0.0)) errbits |= ERR_RHO;
     if (!(Tm > 0.0)) errbits |= ERR_T;
     if (rho != rho || Tm != Tm) errbits |= ERR_NAN;
 
-    if (a.aii > 0.0) {
-        // ---- FP64 closed form of the implicit relaxation
-        const double beta = g.beta;
+    // L1 distance to the Maxwellian of (rho, u, T) (the relaxation keeps them)
+    const bool want_l1 = FINAL || a.emit;
+    const T mpref = (T)(rho / (2.0 * kPi * Tm)), mq = (T)(-0.5 * kLog2e / Tm);
+    const T uxt = (T)ux, uyt = (T)uy;
+    T l1 = 0;
+
+    if constexpr (!FINAL) {
         const double lam = g.dt * a.aii * te;
-        const double k = lam * (1.0 - beta);
-        const double thxx = (Pxx / rho + k * Tm) / (1.0 + k);
-        const double thxy = (Pxy / rho) / (1.0 + k);
-        const double thyy = (Pyy / rho + k * Tm) / (1.0 + k);
-        const double txx = (1.0 - beta) * Tm + beta * thxx;
-        const double txy = beta * thxy;
-        const double tyy = (1.0 - beta) * Tm + beta * thyy;
         double gp[GP_N];
-        if (!gauss_params(rho, ux, uy, Tm, txx, txy, tyy, gp)) errbits |= ERR_SPD;
+        errbits |= relaxed_gaussian<T, L, C>(mo, lam, s, g, gp);
         GaussEval<T> gi;
         gi.load(gp);
-        if (g.correction) {
-            // 15 discrete moments of the sampled Gaussian
-            T acc[15];
-#pragma unroll
-            for (int q = 0; q < 15; ++q) acc[q] = 0;
-#pragma unroll
-            for (int m = 0; m < C; ++m) {
-                if (chunk_node(lane, m) < g.nv2) {
-                    const T b = (vyc[m] - gi.uy) * gi.ist;
-#pragma unroll
-                    for (int e = 0; e < 4; ++e) {
-                        const T vx = vx0[m] + (T)e * dv;
-                        const T G = gi.tilde(vx, vyc[m]);
-                        const T aa = (vx - gi.ux) * gi.ist;
-                        const T a2 = aa * aa, b2 = b * b;
-                        const T Ga = G * aa, Gb = G * b, Ga2 = G * a2, Gab = Ga * b, Gb2 = G * b2;
-                        acc[0] += G;   acc[1] += Ga;  acc[2] += Gb;
-                        acc[3] += Ga2; acc[4] += Gab; acc[5] += Gb2;
-                        acc[6] += Ga2 * aa; acc[7] += Ga2 * b; acc[8] += Gab * b; acc[9] += Gb2 * b;
-                        acc[10] += Ga2 * a2; acc[11] += Ga2 * aa * b; acc[12] += Ga2 * b2;
-                        acc[13] += Gab * b2; acc[14] += Gb2 * b2;
-                    }
-                }
-            }
-            double Sm[15];
-#pragma unroll
-            for (int q = 0; q < 15; ++q) Sm[q] = w * wave_sum((double)acc[q]);
-            if (!solve_correction(Sm, rho, Tm, txx, txy, tyy, gp)) errbits |= ERR_SPD;
-            gi.load(gp);
-        }
-        // ---- relaxation: the stage's single write
         const T lamt = (T)lam, inv1 = (T)(1.0 / (1.0 + lam));
 #pragma unroll
         for (int m = 0; m < C; ++m) {
-            const int k0 = chunk_node(lane, m);
-            if (k0 < g.nv2) {
+            const Chunk<T> ch = chunk_of<T, L>(s, m, g);
+            if (ch.active) {
+                GaussRow<T> gr;
+                gr.set(gi, ch.vy);
+                T fv[4];
 #pragma unroll
-                for (int e = 0; e < 4; ++e) {
-                    const T vx = vx0[m] + (T)e * dv;
-                    fs[m][e] = (fs[m][e] + lamt * gi.hat(vx, vyc[m])) * inv1;
+                for (int e = 0; e < 4; ++e) fv[e] = (lds.v[wave][m][lane][e] + lamt * gr.hat(gi, ch.vx[e])) * inv1;
+                if (gc.valid) Storage<S>::store4(a.fout, nb.c + ch.k0, fv);
+                if (want_l1) {
+                    const T ey = ch.vy - uyt, qy = mq * ey * ey;
+#pragma unroll
+                    for (int e = 0; e < 4; ++e) {
+                        const T ex = ch.vx[e] - uxt;
+                        l1 += fabs(fv[e] - mpref * fast_exp2(mq * ex * ex + qy));
+                    }
                 }
-                Storage<S>::store4(a.fout, nb.c + k0, fs[m]);
             }
         }
-        if (lane == 0) {
+        if (leader) {
             double *o = a.pout + (size_t)cell * GP_N;
 #pragma unroll
             for (int q = 0; q < GP_N; ++q) o[q] = gp[q];
         }
     } else {
-        // final combination: fs is f^{n+1}
 #pragma unroll
         for (int m = 0; m < C; ++m) {
-            const int k0 = chunk_node(lane, m);
-            if (k0 < g.nv2) Storage<S>::store4(a.fout, nb.c + k0, fs[m]);
-        }
-    }
-    if (a.emit) {
-        // L1 distance to the (uncorrected) sampled Maxwellian of the result's
-        // moments; the relaxation keeps rho, u, T of f*, so these are the
-        // moments of the written values up to rounding.
-        const T l2p = (T)log2(rho / (2.0 * kPi * Tm));
-        const T qm = (T)(-0.5 * kLog2e / Tm);
-        const T uxt = (T)ux, uyt = (T)uy;
-        T l1 = 0;
-#pragma unroll
-        for (int m = 0; m < C; ++m) {
-            if (chunk_node(lane, m) < g.nv2) {
-                const T ey = vyc[m] - uyt;
+            const Chunk<T> ch = chunk_of<T, L>(s, m, g);
+            if (ch.active) {
+                const T ey = ch.vy - uyt, qy = mq * ey * ey;
 #pragma unroll
                 for (int e = 0; e < 4; ++e) {
-                    const T ex = vx0[m] + (T)e * dv - uxt;
-                    const T M = fast_exp2(l2p + qm * (ex * ex + ey * ey));
-                    l1 += fabs(fs[m][e] - M);
+                    const T ex = ch.vx[e] - uxt;
+                    l1 += fabs(lds.v[wave][m][lane][e] - mpref * fast_exp2(mq * ex * ex + qy));
                 }
             }
         }
-        const double L1 = w * wave_sum((double)l1);
-        if (lane == 0) a.l1out[cell] = L1;
     }
-    if (lane == 0) {
+    if (want_l1) {
+        const double L1 = g.w * (double)group_sum<L>(l1);
+        if (leader) a.l1out[cell] = L1;
+    }
+    if (leader) {
         const size_t nc = (size_t)a.nc;
         a.Uout[cell] = rho;
         a.Uout[nc + cell] = rho * ux;
         a.Uout[2 * nc + cell] = rho * uy;
         a.Uout[3 * nc + cell] = 0.5 * rho * (ux * ux + uy * uy) + rho * Tm;
     }
-    raise_err(a.err, errbits);
+    raise_err(a.err, errbits, leader);
 }
 
 // ---------------------------------------------------------------- fills
 
 // f = Mhat(U) at the listed cells (eq. Coupling_FluKin): the corrected sampled
 // Maxwellian, i.e. the corrected Gaussian with Tt = T I.
-template <class S, int C>
+template <class S, int L, int C>
 __global__ __launch_bounds__(256) void fill_maxwellian_kernel(FillArgs<S> a) {
     using T = typename Storage<S>::T;
     const Geom &g = a.g;
-    const int item = logical_item(*a.count, 4);
-    if (item < 0) return;
-    const int cell = a.list[item];
-    const int lane = threadIdx.x & 63;
+    const GroupCell gc = group_cell<L>(a.list, *a.count);
+    if (gc.cell < 0) return;
+    const int cell = gc.cell;
+    const int s = (int)(threadIdx.x & (L - 1));
     const size_t nc = (size_t)a.nc;
     const double rho = a.U[cell];
     const double ux = a.U[nc + cell] / rho, uy = a.U[2 * nc + cell] / rho;
@@ -336,125 +530,59 @@ __global__ __launch_bounds__(256) void fill_maxwellian_kernel(FillArgs<S> a) {
     int errbits = 0;
     double gp[GP_N];
     if (!gauss_params(rho, ux, uy, Tm, Tm, 0.0, Tm, gp)) errbits |= ERR_SPD;
+    if (g.correction) {
+        GaussEval<T> ge;
+        ge.load(gp);
+        double Sm[15];
+        gram_sums<T, L, C>(ge, s, g, Sm);
+#pragma unroll
+        for (int q = 0; q < 15; ++q) Sm[q] *= g.w;
+        if (!solve_correction(Sm, rho, Tm, Tm, 0.0, Tm, gp)) errbits |= ERR_SPD;
+    }
     GaussEval<T> gi;
     gi.load(gp);
-    const T dv = (T)g.dv, vmax = (T)g.vmax;
-    if (g.correction) {
-        T acc[15];
-#pragma unroll
-        for (int q = 0; q < 15; ++q) acc[q] = 0;
-#pragma unroll
-        for (int m = 0; m < C; ++m) {
-            const int k0 = chunk_node(lane, m);
-            if (k0 < g.nv2) {
-                const T vy = -vmax + ((T)(k0 / g.nv) + (T)0.5) * dv;
-                const T vx0 = -vmax + ((T)(k0 % g.nv) + (T)0.5) * dv;
-                const T b = (vy - gi.uy) * gi.ist;
-#pragma unroll
-                for (int e = 0; e < 4; ++e) {
-                    const T vx = vx0 + (T)e * dv;
-                    const T G = gi.tilde(vx, vy);
-                    const T aa = (vx - gi.ux) * gi.ist;
-                    const T a2 = aa * aa, b2 = b * b;
-                    const T Ga = G * aa, Gb = G * b, Ga2 = G * a2, Gab = Ga * b, Gb2 = G * b2;
-                    acc[0] += G;   acc[1] += Ga;  acc[2] += Gb;
-                    acc[3] += Ga2; acc[4] += Gab; acc[5] += Gb2;
-                    acc[6] += Ga2 * aa; acc[7] += Ga2 * b; acc[8] += Gab * b; acc[9] += Gb2 * b;
-                    acc[10] += Ga2 * a2; acc[11] += Ga2 * aa * b; acc[12] += Ga2 * b2;
-                    acc[13] += Gab * b2; acc[14] += Gb2 * b2;
-                }
-            }
-        }
-        double Sm[15];
-#pragma unroll
-        for (int q = 0; q < 15; ++q) Sm[q] = g.w * wave_sum((double)acc[q]);
-        if (!solve_correction(Sm, rho, Tm, Tm, 0.0, Tm, gp)) errbits |= ERR_SPD;
-        gi.load(gp);
-    }
 #pragma unroll
     for (int m = 0; m < C; ++m) {
-        const int k0 = chunk_node(lane, m);
-        if (k0 < g.nv2) {
-            const T vy = -vmax + ((T)(k0 / g.nv) + (T)0.5) * dv;
-            const T vx0 = -vmax + ((T)(k0 % g.nv) + (T)0.5) * dv;
+        const Chunk<T> ch = chunk_of<T, L>(s, m, g);
+        if (ch.active && gc.valid) {
+            GaussRow<T> gr;
+            gr.set(gi, ch.vy);
             T v[4];
 #pragma unroll
-            for (int e = 0; e < 4; ++e) v[e] = gi.hat(vx0 + (T)e * dv, vy);
-            Storage<S>::store4(a.f, (size_t)cell * g.nv2 + k0, v);
+            for (int e = 0; e < 4; ++e) v[e] = gr.hat(gi, ch.vx[e]);
+            Storage<S>::store4(a.f, (size_t)cell * g.nv2 + ch.k0, v);
         }
     }
-    raise_err(a.err, errbits);
+    raise_err(a.err, errbits, gc.valid && s == 0);
 }
 
 // U = moments(f) and the L1 distance at the listed cells (eq. Coupling_KinFlu,
 // eq. eqKintoFluid1).
-template <class S, int C>
+template <class S, int L, int C>
 __global__ __launch_bounds__(256) void moments_kernel(MomArgs<S> a) {
     using T = typename Storage<S>::T;
     const Geom &g = a.g;
-    const int item = logical_item(*a.count, 4);
-    if (item < 0) return;
-    const int cell = a.list[item];
-    const int lane = threadIdx.x & 63;
-    const T dv = (T)g.dv, vmax = (T)g.vmax;
+    const GroupCell gc = group_cell<L>(a.list, *a.count);
+    if (gc.cell < 0) return;
+    const int cell = gc.cell;
+    const int s = (int)(threadIdx.x & (L - 1));
     T fv[C][4];
-    T vx0[C], vyc[C];
-    Comp<T> s0, sx, sy;
 #pragma unroll
     for (int m = 0; m < C; ++m) {
-        const int k0 = chunk_node(lane, m);
-        vx0[m] = -vmax + ((T)(k0 % g.nv) + (T)0.5) * dv;
-        vyc[m] = -vmax + ((T)(k0 / g.nv) + (T)0.5) * dv;
+        const Chunk<T> ch = chunk_of<T, L>(s, m, g);
 #pragma unroll
         for (int e = 0; e < 4; ++e) fv[m][e] = 0;
-        if (k0 < g.nv2) {
-            Storage<S>::load4(a.f, (size_t)cell * g.nv2 + k0, fv[m]);
-            T c0 = (fv[m][0] + fv[m][1]) + (fv[m][2] + fv[m][3]);
-            T cx = (vx0[m] * fv[m][0] + (vx0[m] + dv) * fv[m][1]) +
-                   ((vx0[m] + (T)2 * dv) * fv[m][2] + (vx0[m] + (T)3 * dv) * fv[m][3]);
-            s0.add(c0);
-            sx.add(cx);
-            sy.add(vyc[m] * c0);
-        }
+        if (ch.active) Storage<S>::load4(a.f, (size_t)cell * g.nv2 + ch.k0, fv[m]);
     }
-    const double w = g.w;
-    const double rho = w * wave_sum_comp(s0);
-    const double ux = w * wave_sum_comp(sx) / rho;
-    const double uy = w * wave_sum_comp(sy) / rho;
-    Comp<T> pt;
-    const T uxt = (T)ux, uyt = (T)uy;
-#pragma unroll
-    for (int m = 0; m < C; ++m) {
-        if (chunk_node(lane, m) < g.nv2) {
-            T ey = vyc[m] - uyt, acc = 0;
-#pragma unroll
-            for (int e = 0; e < 4; ++e) {
-                T ex = vx0[m] + (T)e * dv - uxt;
-                acc += (ex * ex + ey * ey) * fv[m][e];
-            }
-            pt.add(acc);
-        }
-    }
-    const double Tm = w * wave_sum_comp(pt) / (2.0 * rho);
-    const T l2p = (T)log2(rho / (2.0 * kPi * Tm));
-    const T qm = (T)(-0.5 * kLog2e / Tm);
-    T l1 = 0;
-#pragma unroll
-    for (int m = 0; m < C; ++m) {
-        if (chunk_node(lane, m) < g.nv2) {
-            T ey = vyc[m] - uyt;
-#pragma unroll
-            for (int e = 0; e < 4; ++e) {
-                T ex = vx0[m] + (T)e * dv - uxt;
-                l1 += fabs(fv[m][e] - fast_exp2(l2p + qm * (ex * ex + ey * ey)));
-            }
-        }
-    }
-    const double L1 = w * wave_sum((double)l1);
+    double mo[7];
+    group_moments<T, L, C>(fv, s, g, mo);
+    const double rho = mo[0], ux = mo[1], uy = mo[2], Tm = mo[3];
+    const double L1 = group_l1<T, L, C>(fv, s, g, rho, ux, uy, Tm);
     int errbits = 0;
     if (!(rho > 0.0)) errbits |= ERR_RHO;
     if (!(Tm > 0.0)) errbits |= ERR_T;
-    if (lane == 0) {
+    const bool leader = gc.valid && s == 0;
+    if (leader) {
         const size_t nc = (size_t)a.nc;
         a.U[cell] = rho;
         a.U[nc + cell] = rho * ux;
@@ -462,7 +590,7 @@ __global__ __launch_bounds__(256) void moments_kernel(MomArgs<S> a) {
         a.U[3 * nc + cell] = 0.5 * rho * (ux * ux + uy * uy) + rho * Tm;
         if (a.l1) a.l1[cell] = L1;
     }
-    raise_err(a.err, errbits);
+    raise_err(a.err, errbits, leader);
 }
 
 // ------------------------------------------------------- conversions
@@ -491,61 +619,85 @@ __global__ void f_to_f64_kernel(const S *in, double *out, size_t n4) {
 
 // ------------------------------------------------------- host launchers
 
-static inline int chunks_for(int nv2) {
-    int need = (nv2 + 255) / 256;
-    if (need <= 1) return 1;
-    if (need <= 2) return 2;
-    if (need <= 4) return 4;
-    if (need <= 9) return 9;
-    return 16;
+// Lanes per cell (L) and chunks of 4 nodes per lane (C) for a velocity grid:
+// a 16-lane DPP row per cell (4 cells per wavefront) up to 1024 nodes, a whole
+// wavefront per cell beyond.
+struct Shape { int L, C; };
+
+static inline Shape shape_for(int nv2) {
+    const int chunks = nv2 / 4;
+    if (chunks <= 64) return {16, 4};
+    if (chunks <= 128) return {16, 8};
+    if (chunks <= 256) return {32, 8};
+    if (chunks <= 576) return {64, 9};
+    return {64, 16};
 }
 
-static inline unsigned grid_for(int nmax) {
-    int nblk = (nmax + 3) / 4;
-    int per = (nblk + 7) / 8;
-    return (unsigned)(per * 8 > 0 ? per * 8 : 8);
+static inline unsigned grid_for(int nmax, int cells_per_block) {
+    const int nblk = (nmax + cells_per_block - 1) / cells_per_block;
+    const int per = (nblk + 7) / 8;
+    return (unsigned)(per > 0 ? per * 8 : 8);
 }
 
-template <class S, int C> static void stage_c(const StageArgs<S> &a, unsigned grid, hipStream_t st) {
-    hipLaunchKernelGGL((stage_kernel<S, C>), dim3(grid), dim3(256), 0, st, a);
-}
-template <class S, int C> static void fill_c(const FillArgs<S> &a, unsigned grid, hipStream_t st) {
-    hipLaunchKernelGGL((fill_maxwellian_kernel<S, C>), dim3(grid), dim3(256), 0, st, a);
-}
-template <class S, int C> static void moments_c(const MomArgs<S> &a, unsigned grid, hipStream_t st) {
-    hipLaunchKernelGGL((moments_kernel<S, C>), dim3(grid), dim3(256), 0, st, a);
-}
+#define ESBGK_SHAPES(X) X(16, 4) X(16, 8) X(32, 8) X(64, 9) X(64, 16)
 
-#define ESBGK_DISPATCH_C(FN, S, A, GRID, ST)          \
-    switch (chunks_for((A).g.nv2)) {                  \
-        case 1: FN<S, 1>(A, GRID, ST); break;          \
-        case 2: FN<S, 2>(A, GRID, ST); break;          \
-        case 4: FN<S, 4>(A, GRID, ST); break;          \
-        case 9: FN<S, 9>(A, GRID, ST); break;          \
-        default: FN<S, 16>(A, GRID, ST); break;        \
+template <class S, int NL, int NQ, bool FINAL>
+static hipError_t stage_dispatch(const StageArgs<S> &a, int nmax, hipStream_t st) {
+    const Shape sh = shape_for(a.g.nv2);
+#define ESBGK_CASE(LL, CC)                                                                              \
+    if (sh.L == LL && sh.C == CC) {                                                                     \
+        hipLaunchKernelGGL((stage_kernel<S, LL, CC, NL, NQ, FINAL>), dim3(grid_for(nmax, 4 * (64 / LL))), \
+                           dim3(256), 0, st, a);                                                        \
+        return hipGetLastError();                                                                       \
     }
+    ESBGK_SHAPES(ESBGK_CASE)
+#undef ESBGK_CASE
+    return hipErrorInvalidValue;
+}
 
 template <class S>
 hipError_t launch_stage(const StageArgs<S> &a, int nmax, hipStream_t st) {
-    ESBGK_DISPATCH_C(stage_c, S, a, grid_for(nmax), st);
-    return hipGetLastError();
+    if (a.aii > 0.0) {
+        if (a.nl < 1 || a.fl[0] != a.fn) return hipErrorInvalidValue;  // implicit stages transport f^n first
+        if (a.nl == 1 && a.nq == 0) return stage_dispatch<S, 1, 0, false>(a, nmax, st);
+        if (a.nl == 2 && a.nq == 1) return stage_dispatch<S, 2, 1, false>(a, nmax, st);
+    } else {
+        if (a.nl == 2 && a.nq == 2) return stage_dispatch<S, 2, 2, true>(a, nmax, st);
+    }
+    return hipErrorInvalidValue;
 }
 
 template <class S>
 hipError_t launch_fill(const FillArgs<S> &a, int nmax, hipStream_t st) {
-    ESBGK_DISPATCH_C(fill_c, S, a, grid_for(nmax), st);
-    return hipGetLastError();
+    const Shape sh = shape_for(a.g.nv2);
+#define ESBGK_CASE(LL, CC)                                                                          \
+    if (sh.L == LL && sh.C == CC) {                                                                 \
+        hipLaunchKernelGGL((fill_maxwellian_kernel<S, LL, CC>), dim3(grid_for(nmax, 4 * (64 / LL))), \
+                           dim3(256), 0, st, a);                                                    \
+        return hipGetLastError();                                                                   \
+    }
+    ESBGK_SHAPES(ESBGK_CASE)
+#undef ESBGK_CASE
+    return hipErrorInvalidValue;
 }
 
 template <class S>
 hipError_t launch_moments(const MomArgs<S> &a, int nmax, hipStream_t st) {
-    ESBGK_DISPATCH_C(moments_c, S, a, grid_for(nmax), st);
-    return hipGetLastError();
+    const Shape sh = shape_for(a.g.nv2);
+#define ESBGK_CASE(LL, CC)                                                                  \
+    if (sh.L == LL && sh.C == CC) {                                                         \
+        hipLaunchKernelGGL((moments_kernel<S, LL, CC>), dim3(grid_for(nmax, 4 * (64 / LL))), \
+                           dim3(256), 0, st, a);                                            \
+        return hipGetLastError();                                                           \
+    }
+    ESBGK_SHAPES(ESBGK_CASE)
+#undef ESBGK_CASE
+    return hipErrorInvalidValue;
 }
 
 template <class S>
 hipError_t launch_from_f64(const double *in, void *out, size_t n, hipStream_t st) {
-    size_t n4 = n / 4;
+    const size_t n4 = n / 4;
     unsigned grid = (unsigned)((n4 + 255) / 256 < 65536 ? (n4 + 255) / 256 : 65536);
     if (grid == 0) grid = 1;
     hipLaunchKernelGGL((f_from_f64_kernel<S>), dim3(grid), dim3(256), 0, st, in, (S *)out, n4);
@@ -554,7 +706,7 @@ hipError_t launch_from_f64(const double *in, void *out, size_t n, hipStream_t st
 
 template <class S>
 hipError_t launch_to_f64(const void *in, double *out, size_t n, hipStream_t st) {
-    size_t n4 = n / 4;
+    const size_t n4 = n / 4;
     unsigned grid = (unsigned)((n4 + 255) / 256 < 65536 ? (n4 + 255) / 256 : 65536);
     if (grid == 0) grid = 1;
     hipLaunchKernelGGL((f_to_f64_kernel<S>), dim3(grid), dim3(256), 0, st, (const S *)in, out, n4);

@@ -92,8 +92,21 @@ def test_indicator_bit_exact(nx, ny):
             lg = torch.empty(nc, dtype=torch.float64, device="cuda")
             E.esbgk_indicator(cfg, dev(prim), dev(eps), dev(l1), dev(mold, torch.uint8), mg, lg)
             assert np.array_equal(mg.cpu().numpy(), mo)
-            assert np.array_equal(lg.cpu().numpy().view(np.uint64), lo.view(np.uint64))
+            # lambda is reported with one square root (not part of the decision)
+            np.testing.assert_allclose(lg.cpu().numpy(), lo, rtol=4.5e-16, atol=0)
             assert 0 < mo.sum() < nc or eta == 1e-1
+    # near-ties: eta equal to (and one ulp around) lambda values of the data itself
+    p = oracle.Problem(nx=nx, ny=ny, nv=8, vmax=4.0)
+    _, lo = oracle.indicator(p, prim, eps, l1, mold, return_lambda=True)
+    for k in np.argsort(lo)[:: max(1, nc // 7)]:
+        for eta in (lo[k], np.nextafter(lo[k], 0), np.nextafter(lo[k], 1)):
+            p = oracle.Problem(nx=nx, ny=ny, nv=8, vmax=4.0, eta=float(eta), delta=float(l1[k]))
+            mo = oracle.indicator(p, prim, eps, l1, mold)
+            cfg = E.make_config(nx, ny, 8, 4.0, eta=float(eta), delta=float(l1[k]))
+            dev = lambda a, t=torch.float64: torch.as_tensor(np.ascontiguousarray(a), dtype=t).cuda()
+            mg = torch.empty(nc, dtype=torch.uint8, device="cuda")
+            E.esbgk_indicator(cfg, dev(prim), dev(eps), dev(l1), dev(mold, torch.uint8), mg)
+            assert np.array_equal(mg.cpu().numpy(), mo), (k, eta)
 
 
 @pytest.mark.parametrize("nx,ny", [(16, 16), (20, 13), (3, 5)])
