@@ -1,4 +1,6 @@
-// kinetic.hip -- phase-space kernels of the kinetic IMEX stage (ES-BGK, 2D2V).
+// kinetic_impl.h -- phase-space kernels of the kinetic IMEX stage (ES-BGK, 2D2V),
+// instantiated per storage precision by kinetic_f64.hip, kinetic_f32.hip and
+// kinetic_bf16.hip.
 //
 // stage_kernel fuses, for every kinetic cell (one L-lane group per cell):
 //   transport L(f^(j)) of earlier stages at every node (upwind or minmod-limited
@@ -16,11 +18,12 @@
 // The FINAL variant is the final combination (eq. RKEI2): it writes f^{n+1},
 // its moments U^{n+1} and the L1 distance to the Maxwellian that the next
 // regime update reads (eq. eqKintoFluid1).
+#pragma once
 #include "kernels.h"
 
 // waves per SIMD the stage kernels are compiled for (caps their VGPR budget)
 #ifndef ESBGK_STAGE_MIN_WAVES
-#define ESBGK_STAGE_MIN_WAVES 4
+#define ESBGK_STAGE_MIN_WAVES 3
 #endif
 
 namespace esbgk {
@@ -61,6 +64,7 @@ template <class T> __device__ inline T limited_diff(T far, T up, T c, T dn) {
 template <class T> struct Chunk {
     int k0;
     bool active;
+    bool xpos, ypos, straddle;  // upwind directions; straddle: v_x changes sign inside the chunk
     T vx[4], vy;
 };
 
@@ -74,7 +78,7 @@ __device__ inline void transport4(const S *f, const Nbr &nb, const Chunk<typenam
     const int k0 = ch.k0;
     Storage<S>::load4(f, nb.c + k0, fc);
     // y: one velocity per chunk, pick the upwind / downwind / far neighbours
-    const bool ypos = ch.vy > (T)0;
+    const bool ypos = ch.ypos;
     const T avy = (ypos ? ch.vy : -ch.vy) * idy;
     T yu[4];
     Storage<S>::load4(f, (ypos ? nb.ym1 : nb.yp1) + k0, yu);
@@ -90,9 +94,8 @@ __device__ inline void transport4(const S *f, const Nbr &nb, const Chunk<typenam
         for (int e = 0; e < 4; ++e) Ly[e] = avy * limited_diff(yf[e], yu[e], fc[e], yd[e]);
     }
     // x: the 4 nodes of a chunk share the sign of v_x unless the chunk straddles 0
-    const bool anypos = ch.vx[3] > (T)0, anyneg = ch.vx[0] < (T)0;
-    if (!(anypos && anyneg)) {
-        const bool pos = anypos;
+    if (!ch.straddle) {
+        const bool pos = ch.xpos;
         T xu[4];
         Storage<S>::load4(f, (pos ? nb.xm1 : nb.xp1) + k0, xu);
         if (recon == 0) {
@@ -174,15 +177,36 @@ template <int L> __device__ inline GroupCell group_cell(const int *list, int cou
     return gc;
 }
 
-// Chunk m of sub-lane s.
-template <class T, int L>
+// Chunk m of sub-lane s.  NV > 0 is the velocity grid size known at compile
+// time: when L is a multiple of NV/4 every lane keeps the same x-velocities in
+// all its chunks and each chunk's y-row (hence its upwind direction) is a
+// compile-time function of m, so neighbour selection and addressing fold into
+// constants.  NV = 0 reads the size from g.
+template <class T, int L, int NV>
 __device__ inline Chunk<T> chunk_of(int s, int m, const Geom &g) {
     Chunk<T> ch;
     const int c = s + L * m;
     ch.k0 = 4 * c;
-    ch.active = ch.k0 < g.nv2;
-    const int nq4 = g.nv >> 2;
-    const int ia = 4 * (c % nq4), ib = c / nq4;
+    const int nv = NV > 0 ? NV : g.nv;
+    const int nq4 = nv >> 2;
+    int ia, ib;
+    if constexpr (NV > 0 && (L % (NV / 4)) == 0) {
+        ia = 4 * (s % (NV / 4));
+        ib = s / (NV / 4) + m * (L / (NV / 4));
+        ch.active = ch.k0 < NV * NV;
+    } else {
+        ia = 4 * (c % nq4);
+        ib = c / nq4;
+        ch.active = ch.k0 < nv * nv;
+    }
+    const int half = nv >> 1;
+    ch.xpos = ia >= half;
+    ch.straddle = (NV > 0 && NV % 8 == 0) ? false : (ia < half && ia + 3 >= half);
+    if constexpr (NV > 0 && (L % (NV / 4)) == 0 && ((NV / 2) % (L / (NV / 4))) == 0) {
+        ch.ypos = m * (L / (NV / 4)) >= NV / 2;  // the rows of chunk slice m lie on one side
+    } else {
+        ch.ypos = ib >= half;
+    }
     const T dv = (T)g.dv, v0 = (T)(-g.vmax + 0.5 * g.dv);
     ch.vy = v0 + (T)ib * dv;
 #pragma unroll
@@ -194,14 +218,14 @@ __device__ inline Chunk<T> chunk_of(int s, int m, const Geom &g) {
 // sampled Gaussian over the group's nodes (weight and prefactor are applied by
 // the caller); the six of order <= 2 are compensated.  Order of S:
 // 00 10 01 20 11 02 30 21 12 03 40 31 22 13 04.
-template <class T, int L, int C>
+template <class T, int L, int C, int NV>
 __device__ inline void gram_sums(const GaussEval<T> &ge, int s, const Geom &g, double S[15]) {
     Comp<T> lowc[6];
     T low[6] = {0, 0, 0, 0, 0, 0};
     T high[9] = {0, 0, 0, 0, 0, 0, 0, 0, 0};
 #pragma unroll
     for (int m = 0; m < C; ++m) {
-        const Chunk<T> ch = chunk_of<T, L>(s, m, g);
+        const Chunk<T> ch = chunk_of<T, L, NV>(s, m, g);
         if (ch.active) {
             GaussRow<T> gr;
             gr.set(ge, ch.vy);
@@ -234,13 +258,13 @@ __device__ inline void gram_sums(const GaussEval<T> &ge, int s, const Geom &g, d
 
 // Group-wide moments of the values v: compensated sums of f, v f and the raw
 // second moments, centred in FP64.  out = {rho, ux, uy, T, Thxx, Thxy, Thyy}.
-template <class T, int L, int C>
+template <class T, int L, int C, int NV>
 __device__ inline void group_moments(const T v[C][4], int s, const Geom &g, double out[7]) {
     Comp<T> cs[6];
     T part[6] = {0, 0, 0, 0, 0, 0};
 #pragma unroll
     for (int m = 0; m < C; ++m) {
-        const Chunk<T> ch = chunk_of<T, L>(s, m, g);
+        const Chunk<T> ch = chunk_of<T, L, NV>(s, m, g);
         if (ch.active) {
             const T c0 = (v[m][0] + v[m][1]) + (v[m][2] + v[m][3]);
             const T cx = (ch.vx[0] * v[m][0] + ch.vx[1] * v[m][1]) + (ch.vx[2] * v[m][2] + ch.vx[3] * v[m][3]);
@@ -276,7 +300,7 @@ __device__ inline void group_moments(const T v[C][4], int s, const Geom &g, doub
 
 // L1 distance (eq. eqKintoFluid1) of the values v to the sampled Maxwellian
 // with moments (rho, u, T), over the group's nodes.
-template <class T, int L, int C>
+template <class T, int L, int C, int NV>
 __device__ inline double group_l1(const T v[C][4], int s, const Geom &g, double rho, double ux, double uy,
                                   double Tm) {
     const T pref = (T)(rho / (2.0 * kPi * Tm));
@@ -285,7 +309,7 @@ __device__ inline double group_l1(const T v[C][4], int s, const Geom &g, double 
     T l1 = 0;
 #pragma unroll
     for (int m = 0; m < C; ++m) {
-        const Chunk<T> ch = chunk_of<T, L>(s, m, g);
+        const Chunk<T> ch = chunk_of<T, L, NV>(s, m, g);
         if (ch.active) {
             const T ey = ch.vy - uyt;
             const T qy = qm * ey * ey;
@@ -301,7 +325,7 @@ __device__ inline double group_l1(const T v[C][4], int s, const Geom &g, double 
 
 // FP64 Gaussian parameters of the relaxed state and its conservation
 // correction; returns the error bits.
-template <class T, int L, int C>
+template <class T, int L, int C, int NV>
 __device__ inline int relaxed_gaussian(const double mo[7], double lam, int s, const Geom &g, double gp[GP_N]) {
     const double beta = g.beta;
     const double rho = mo[0], ux = mo[1], uy = mo[2], Tm = mo[3];
@@ -319,7 +343,7 @@ __device__ inline int relaxed_gaussian(const double mo[7], double lam, int s, co
         GaussEval<T> ge;
         ge.load(gp);
         double S[15];
-        gram_sums<T, L, C>(ge, s, g, S);
+        gram_sums<T, L, C, NV>(ge, s, g, S);
 #pragma unroll
         for (int q = 0; q < 15; ++q) S[q] *= g.w;
         if (!solve_correction(S, rho, Tm, txx, txy, tyy, gp)) err |= ERR_SPD;
@@ -376,7 +400,7 @@ template <class T, int C> struct StageLds {
     T v[4][C][64][4];  // [wave in block][chunk][lane][node]
 };
 
-template <class S, int L, int C, int NL, int NQ, bool FINAL>
+template <class S, int NV, int L, int C, int NL, int NQ, bool FINAL>
 __global__ __launch_bounds__(256, ESBGK_STAGE_MIN_WAVES) void stage_kernel(StageArgs<S> a) {
     using T = typename Storage<S>::T;
     __shared__ StageLds<T, C> lds;
@@ -400,7 +424,7 @@ __global__ __launch_bounds__(256, ESBGK_STAGE_MIN_WAVES) void stage_kernel(Stage
     MomentAcc<T> macc;
 #pragma unroll
     for (int m = 0; m < C; ++m) {
-        const Chunk<T> ch = chunk_of<T, L>(s, m, g);
+        const Chunk<T> ch = chunk_of<T, L, NV>(s, m, g);
         if (ch.active) {
             T base[4], acc[4] = {0, 0, 0, 0}, fs[4];
 #pragma unroll
@@ -434,6 +458,9 @@ __global__ __launch_bounds__(256, ESBGK_STAGE_MIN_WAVES) void stage_kernel(Stage
             if (FINAL && gc.valid) Storage<S>::store4(a.fout, nb.c + ch.k0, fs);
         }
         if ((m & 3) == 3) macc.fold();
+        // keep each chunk's stencil loads inside its iteration: bounded register
+        // use, latency hidden by the other wavefronts of the CU
+        __builtin_amdgcn_sched_barrier(0);
     }
 
     // ---- moments of f*
@@ -454,13 +481,13 @@ __global__ __launch_bounds__(256, ESBGK_STAGE_MIN_WAVES) void stage_kernel(Stage
     if constexpr (!FINAL) {
         const double lam = g.dt * a.aii * te;
         double gp[GP_N];
-        errbits |= relaxed_gaussian<T, L, C>(mo, lam, s, g, gp);
+        errbits |= relaxed_gaussian<T, L, C, NV>(mo, lam, s, g, gp);
         GaussEval<T> gi;
         gi.load(gp);
         const T lamt = (T)lam, inv1 = (T)(1.0 / (1.0 + lam));
 #pragma unroll
         for (int m = 0; m < C; ++m) {
-            const Chunk<T> ch = chunk_of<T, L>(s, m, g);
+            const Chunk<T> ch = chunk_of<T, L, NV>(s, m, g);
             if (ch.active) {
                 GaussRow<T> gr;
                 gr.set(gi, ch.vy);
@@ -486,7 +513,7 @@ __global__ __launch_bounds__(256, ESBGK_STAGE_MIN_WAVES) void stage_kernel(Stage
     } else {
 #pragma unroll
         for (int m = 0; m < C; ++m) {
-            const Chunk<T> ch = chunk_of<T, L>(s, m, g);
+            const Chunk<T> ch = chunk_of<T, L, NV>(s, m, g);
             if (ch.active) {
                 const T ey = ch.vy - uyt, qy = mq * ey * ey;
 #pragma unroll
@@ -515,7 +542,7 @@ __global__ __launch_bounds__(256, ESBGK_STAGE_MIN_WAVES) void stage_kernel(Stage
 
 // f = Mhat(U) at the listed cells (eq. Coupling_FluKin): the corrected sampled
 // Maxwellian, i.e. the corrected Gaussian with Tt = T I.
-template <class S, int L, int C>
+template <class S, int NV, int L, int C>
 __global__ __launch_bounds__(256) void fill_maxwellian_kernel(FillArgs<S> a) {
     using T = typename Storage<S>::T;
     const Geom &g = a.g;
@@ -534,7 +561,7 @@ __global__ __launch_bounds__(256) void fill_maxwellian_kernel(FillArgs<S> a) {
         GaussEval<T> ge;
         ge.load(gp);
         double Sm[15];
-        gram_sums<T, L, C>(ge, s, g, Sm);
+        gram_sums<T, L, C, NV>(ge, s, g, Sm);
 #pragma unroll
         for (int q = 0; q < 15; ++q) Sm[q] *= g.w;
         if (!solve_correction(Sm, rho, Tm, Tm, 0.0, Tm, gp)) errbits |= ERR_SPD;
@@ -543,7 +570,7 @@ __global__ __launch_bounds__(256) void fill_maxwellian_kernel(FillArgs<S> a) {
     gi.load(gp);
 #pragma unroll
     for (int m = 0; m < C; ++m) {
-        const Chunk<T> ch = chunk_of<T, L>(s, m, g);
+        const Chunk<T> ch = chunk_of<T, L, NV>(s, m, g);
         if (ch.active && gc.valid) {
             GaussRow<T> gr;
             gr.set(gi, ch.vy);
@@ -558,7 +585,7 @@ __global__ __launch_bounds__(256) void fill_maxwellian_kernel(FillArgs<S> a) {
 
 // U = moments(f) and the L1 distance at the listed cells (eq. Coupling_KinFlu,
 // eq. eqKintoFluid1).
-template <class S, int L, int C>
+template <class S, int NV, int L, int C>
 __global__ __launch_bounds__(256) void moments_kernel(MomArgs<S> a) {
     using T = typename Storage<S>::T;
     const Geom &g = a.g;
@@ -569,15 +596,15 @@ __global__ __launch_bounds__(256) void moments_kernel(MomArgs<S> a) {
     T fv[C][4];
 #pragma unroll
     for (int m = 0; m < C; ++m) {
-        const Chunk<T> ch = chunk_of<T, L>(s, m, g);
+        const Chunk<T> ch = chunk_of<T, L, NV>(s, m, g);
 #pragma unroll
         for (int e = 0; e < 4; ++e) fv[m][e] = 0;
         if (ch.active) Storage<S>::load4(a.f, (size_t)cell * g.nv2 + ch.k0, fv[m]);
     }
     double mo[7];
-    group_moments<T, L, C>(fv, s, g, mo);
+    group_moments<T, L, C, NV>(fv, s, g, mo);
     const double rho = mo[0], ux = mo[1], uy = mo[2], Tm = mo[3];
-    const double L1 = group_l1<T, L, C>(fv, s, g, rho, ux, uy, Tm);
+    const double L1 = group_l1<T, L, C, NV>(fv, s, g, rho, ux, uy, Tm);
     int errbits = 0;
     if (!(rho > 0.0)) errbits |= ERR_RHO;
     if (!(Tm > 0.0)) errbits |= ERR_T;
@@ -620,8 +647,8 @@ __global__ void f_to_f64_kernel(const S *in, double *out, size_t n4) {
 // ------------------------------------------------------- host launchers
 
 // Lanes per cell (L) and chunks of 4 nodes per lane (C) for a velocity grid:
-// a 16-lane DPP row per cell (4 cells per wavefront) up to 1024 nodes, a whole
-// wavefront per cell beyond.
+// a 16-lane DPP row per cell (4 cells per wavefront) for up to 256 nodes, a
+// 32-lane half-wavefront per cell up to 1024 nodes, a whole wavefront beyond.
 struct Shape { int L, C; };
 
 static inline Shape shape_for(int nv2) {
@@ -639,17 +666,27 @@ static inline unsigned grid_for(int nmax, int cells_per_block) {
     return (unsigned)(per > 0 ? per * 8 : 8);
 }
 
-#define ESBGK_SHAPES(X) X(16, 4) X(16, 8) X(32, 8) X(64, 9) X(64, 16)
+// Velocity-grid sizes with compile-time instantiations (NV, L, C); any other
+// multiple of 4 runs the NV = 0 kernels with the shape of shape_for().
+// nv = 32: one cell per wavefront (neighbour bases and Gaussian parameters are
+// wave-uniform) measured fastest against 2 cells (32 lanes) and 4 cells (16).
+#ifndef ESBGK_NV32_L
+#define ESBGK_NV32_L 64
+#define ESBGK_NV32_C 4
+#endif
+#define ESBGK_STATIC_NV(X) X(16, 16, 4) X(32, ESBGK_NV32_L, ESBGK_NV32_C) X(48, 64, 9) X(64, 64, 16)
+#define ESBGK_SHAPES(X) X(0, 16, 4) X(0, 16, 8) X(0, 32, 8) X(0, 64, 9) X(0, 64, 16)
 
 template <class S, int NL, int NQ, bool FINAL>
 static hipError_t stage_dispatch(const StageArgs<S> &a, int nmax, hipStream_t st) {
     const Shape sh = shape_for(a.g.nv2);
-#define ESBGK_CASE(LL, CC)                                                                              \
-    if (sh.L == LL && sh.C == CC) {                                                                     \
-        hipLaunchKernelGGL((stage_kernel<S, LL, CC, NL, NQ, FINAL>), dim3(grid_for(nmax, 4 * (64 / LL))), \
-                           dim3(256), 0, st, a);                                                        \
-        return hipGetLastError();                                                                       \
+#define ESBGK_CASE(NN, LL, CC)                                                                                     \
+    if ((NN == 0) ? (sh.L == LL && sh.C == CC) : (a.g.nv == NN)) {                                                    \
+        hipLaunchKernelGGL((stage_kernel<S, NN, LL, CC, NL, NQ, FINAL>), dim3(grid_for(nmax, 4 * (64 / LL))),       \
+                           dim3(256), 0, st, a);                                                                    \
+        return hipGetLastError();                                                                                   \
     }
+    ESBGK_STATIC_NV(ESBGK_CASE)
     ESBGK_SHAPES(ESBGK_CASE)
 #undef ESBGK_CASE
     return hipErrorInvalidValue;
@@ -670,12 +707,13 @@ hipError_t launch_stage(const StageArgs<S> &a, int nmax, hipStream_t st) {
 template <class S>
 hipError_t launch_fill(const FillArgs<S> &a, int nmax, hipStream_t st) {
     const Shape sh = shape_for(a.g.nv2);
-#define ESBGK_CASE(LL, CC)                                                                          \
-    if (sh.L == LL && sh.C == CC) {                                                                 \
-        hipLaunchKernelGGL((fill_maxwellian_kernel<S, LL, CC>), dim3(grid_for(nmax, 4 * (64 / LL))), \
-                           dim3(256), 0, st, a);                                                    \
-        return hipGetLastError();                                                                   \
+#define ESBGK_CASE(NN, LL, CC)                                                                               \
+    if ((NN == 0) ? (sh.L == LL && sh.C == CC) : (a.g.nv == NN)) {                                              \
+        hipLaunchKernelGGL((fill_maxwellian_kernel<S, NN, LL, CC>), dim3(grid_for(nmax, 4 * (64 / LL))),      \
+                           dim3(256), 0, st, a);                                                              \
+        return hipGetLastError();                                                                             \
     }
+    ESBGK_STATIC_NV(ESBGK_CASE)
     ESBGK_SHAPES(ESBGK_CASE)
 #undef ESBGK_CASE
     return hipErrorInvalidValue;
@@ -684,12 +722,13 @@ hipError_t launch_fill(const FillArgs<S> &a, int nmax, hipStream_t st) {
 template <class S>
 hipError_t launch_moments(const MomArgs<S> &a, int nmax, hipStream_t st) {
     const Shape sh = shape_for(a.g.nv2);
-#define ESBGK_CASE(LL, CC)                                                                  \
-    if (sh.L == LL && sh.C == CC) {                                                         \
-        hipLaunchKernelGGL((moments_kernel<S, LL, CC>), dim3(grid_for(nmax, 4 * (64 / LL))), \
-                           dim3(256), 0, st, a);                                            \
-        return hipGetLastError();                                                           \
+#define ESBGK_CASE(NN, LL, CC)                                                                       \
+    if ((NN == 0) ? (sh.L == LL && sh.C == CC) : (a.g.nv == NN)) {                                      \
+        hipLaunchKernelGGL((moments_kernel<S, NN, LL, CC>), dim3(grid_for(nmax, 4 * (64 / LL))),      \
+                           dim3(256), 0, st, a);                                                      \
+        return hipGetLastError();                                                                     \
     }
+    ESBGK_STATIC_NV(ESBGK_CASE)
     ESBGK_SHAPES(ESBGK_CASE)
 #undef ESBGK_CASE
     return hipErrorInvalidValue;
@@ -719,9 +758,5 @@ hipError_t launch_to_f64(const void *in, double *out, size_t n, hipStream_t st) 
     template hipError_t launch_moments<S>(const MomArgs<S> &, int, hipStream_t);             \
     template hipError_t launch_from_f64<S>(const double *, void *, size_t, hipStream_t);     \
     template hipError_t launch_to_f64<S>(const void *, double *, size_t, hipStream_t);
-
-ESBGK_INST(double)
-ESBGK_INST(float)
-ESBGK_INST(bf16_t)
 
 }  // namespace esbgk

@@ -13,7 +13,8 @@ import os
 import torch
 
 _HERE = os.path.dirname(os.path.abspath(__file__))
-LIB_PATH = os.path.join(_HERE, "libesbgk.so")
+# ESBGK_LIB selects another build of the same library (e.g. a tuning variant)
+LIB_PATH = os.environ.get("ESBGK_LIB", os.path.join(_HERE, "libesbgk.so"))
 
 OK, EINVAL, ENOMEM, EDEVICE, ENONPHYS = 0, -1, -2, -3, -4
 ARS222, ARS233 = 0, 1
