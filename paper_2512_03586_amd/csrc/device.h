@@ -218,33 +218,44 @@ __device__ inline bool gauss_params(double rho, double ux, double uy, double T, 
     return ok;
 }
 
-// The conservation correction from the 15 discrete moments
-// S_pq = w sum exp2(Q) a^p b^q (p + q <= 4) of the unscaled sampled Gaussian:
-// Gram matrix A_mn = pref S(psi_m psi_n) of Gtilde = pref exp2(Q), targets
-// t = (rho, 0, 0, rho txx/T, rho txy/T, rho tyy/T); solve A c = t in deviation
-// form A dc = t - A e0 (c = e0 + dc) by Cholesky in FP64, then fold pref into
-// c (gp[GP_C0..GP_C5] = pref * c).  Monomial order of S:
-// 00, 10, 01, 20, 11, 02, 30, 21, 12, 03, 40, 31, 22, 13, 04.
-__device__ inline bool solve_correction(const double S[15], double rho, double T, double txx,
-                                        double txy, double tyy, double *gp) {
+// Correction in deviation form, fast path.  r = t - (discrete moments of the
+// sampled Gaussian up to order 2), scaled by 1/rho; solves M(Sigma) dc = r/rho
+// with M the moment matrix of (1, a, b, a^2, ab, b^2) under the continuous
+// Gaussian N(0, Sigma), Sigma = Tt/T: odd block Sigma itself, even block
+// reduced to the covariance matrix of (a^2, ab, b^2) by eliminating dc0.  The
+// discrete Gram matrix differs from M by the quadrature error, so the result
+// leaves a residual of second order in that error.  All FP64.
+__device__ inline void solve_correction_gaussian(const double rr[6], double sxx, double sxy, double syy,
+                                                 double dc[6]) {
+    const double ids = 1.0 / (sxx * syy - sxy * sxy);
+    dc[1] = (syy * rr[1] - sxy * rr[2]) * ids;
+    dc[2] = (sxx * rr[2] - sxy * rr[1]) * ids;
+    // K d = rhs, K = Cov(a^2, ab, b^2)
+    const double k11 = 2.0 * sxx * sxx, k12 = 2.0 * sxx * sxy, k13 = 2.0 * sxy * sxy;
+    const double k22 = sxx * syy + sxy * sxy, k23 = 2.0 * sxy * syy, k33 = 2.0 * syy * syy;
+    const double b1 = rr[3] - sxx * rr[0], b2 = rr[4] - sxy * rr[0], b3 = rr[5] - syy * rr[0];
+    const double c11 = k22 * k33 - k23 * k23, c12 = k13 * k23 - k12 * k33, c13 = k12 * k23 - k13 * k22;
+    const double c22 = k11 * k33 - k13 * k13, c23 = k12 * k13 - k11 * k23, c33 = k11 * k22 - k12 * k12;
+    const double idet = 1.0 / (k11 * c11 + k12 * c12 + k13 * c13);
+    dc[3] = (c11 * b1 + c12 * b2 + c13 * b3) * idet;
+    dc[4] = (c12 * b1 + c22 * b2 + c23 * b3) * idet;
+    dc[5] = (c13 * b1 + c23 * b2 + c33 * b3) * idet;
+    dc[0] = rr[0] - (sxx * dc[3] + sxy * dc[4] + syy * dc[5]);
+}
+
+// Exact path: the discrete Gram matrix from the 15 moments S (of the scaled
+// sampled Gaussian, order 00 10 01 20 11 02 30 21 12 03 40 31 22 13 04),
+// A dc = r by Cholesky in FP64.  Returns false if A is not SPD.
+__device__ inline bool solve_correction_gram(const double S[15], const double r[6], double dc[6]) {
     const int pp[6] = {0, 1, 0, 2, 1, 0}, qq[6] = {0, 0, 1, 0, 1, 2};
-    const double pref = gp[GP_PREF];
     double A[6][6];
 #pragma unroll
     for (int m = 0; m < 6; ++m)
 #pragma unroll
         for (int n = 0; n <= m; ++n) {
             const int p = pp[m] + pp[n], q = qq[m] + qq[n], d = p + q;
-            A[m][n] = pref * S[d * (d + 1) / 2 + q];
+            A[m][n] = S[d * (d + 1) / 2 + q];
         }
-    const double iT = 1.0 / T;
-    double r[6];
-    r[0] = rho - A[0][0];
-    r[1] = -A[1][0];
-    r[2] = -A[2][0];
-    r[3] = rho * txx * iT - A[3][0];
-    r[4] = rho * txy * iT - A[4][0];
-    r[5] = rho * tyy * iT - A[5][0];
     bool ok = true;
     double il[6];
 #pragma unroll
@@ -270,21 +281,12 @@ __device__ inline bool solve_correction(const double S[15], double rho, double T
         for (int k = 0; k < i; ++k) s -= A[i][k] * y[k];
         y[i] = s * il[i];
     }
-    double x[6];
 #pragma unroll
     for (int i = 5; i >= 0; --i) {
         double s = y[i];
 #pragma unroll
-        for (int k = i + 1; k < 6; ++k) s -= A[k][i] * x[k];
-        x[i] = s * il[i];
-    }
-    if (ok) {
-        gp[GP_C0] = pref * (1.0 + x[0]);
-        gp[GP_C1] = pref * x[1];
-        gp[GP_C2] = pref * x[2];
-        gp[GP_C3] = pref * x[3];
-        gp[GP_C4] = pref * x[4];
-        gp[GP_C5] = pref * x[5];
+        for (int k = i + 1; k < 6; ++k) s -= A[k][i] * dc[k];
+        dc[i] = s * il[i];
     }
     return ok;
 }

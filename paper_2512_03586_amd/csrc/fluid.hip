@@ -86,14 +86,16 @@ __global__ void euler_stage_kernel(EulerArgs a) {
 // ------------------------------------------------------- conversions
 
 // Primitive variables, every operation a correctly rounded IEEE double op in
-// a fixed order (part of the bit-exact indicator contract).
+// a fixed order (part of the bit-exact indicator contract; this file is
+// compiled without contraction, and the expressions are written with plain
+// operators in it so that the setting applies to them).
 __device__ inline void prim_of(double U0, double U1, double U2, double U3, double *rho, double *ux,
                                double *uy, double *T) {
     *rho = U0;
-    *ux = __ddiv_rn(U1, U0);
-    *uy = __ddiv_rn(U2, U0);
-    double k = __dmul_rn(__dmul_rn(0.5, U0), __dadd_rn(__dmul_rn(*ux, *ux), __dmul_rn(*uy, *uy)));
-    *T = __ddiv_rn(__dsub_rn(U3, k), U0);
+    *ux = U1 / U0;
+    *uy = U2 / U0;
+    const double k = (0.5 * U0) * ((*ux) * (*ux) + (*uy) * (*uy));
+    *T = (U3 - k) / U0;
 }
 
 __global__ void prim_kernel(const double *U, double *prim, int nc) {
@@ -125,7 +127,8 @@ __global__ void conserved_kernel(const double *rho, const double *ux, const doub
 // ------------------------------------------------------------- indicator
 
 // Regime indicator of Sec. 3.1.2 at one cell.  The operation order matches the
-// documented contract (no contraction, correctly rounded + - * / only: the
+// documented contract (plain operators in this no-contraction file, correctly
+// rounded + - * / only: the
 // criterion lambda > eta is decided through the square-root-free equivalent
 // eta - |m| < 0 or q > (eta - |m|)^2, and (ck eps/(tau sqrt T))^2 is formed as
 // (ck eps)^2 / (tau^2 T)).
@@ -137,30 +140,30 @@ __device__ inline uint8_t indicator_cell(const IndicatorArgs &a, int cell, doubl
     const size_t cn = (size_t)wrapc(j + 1, ny) * nx + i, cs = (size_t)wrapc(j - 1, ny) * nx + i;
     const double *ux = a.prim + n, *uy = a.prim + 2 * n, *T = a.prim + 3 * n;
     const double twodx = a.twodx, twody = a.twody;
-    const double uxx = __ddiv_rn(__dsub_rn(ux[ce], ux[cw]), twodx);
-    const double uxy = __ddiv_rn(__dsub_rn(ux[cn], ux[cs]), twody);
-    const double uyx = __ddiv_rn(__dsub_rn(uy[ce], uy[cw]), twodx);
-    const double uyy = __ddiv_rn(__dsub_rn(uy[cn], uy[cs]), twody);
-    const double Tx = __ddiv_rn(__dsub_rn(T[ce], T[cw]), twodx);
-    const double Ty = __ddiv_rn(__dsub_rn(T[cn], T[cs]), twody);
-    const double div = __dadd_rn(uxx, uyy);
-    const double Dxx = __dsub_rn(__dadd_rn(uxx, uxx), __dmul_rn(a.cD, div));
-    const double Dxy = __dadd_rn(uxy, uyx);
-    const double Dyy = __dsub_rn(__dadd_rn(uyy, uyy), __dmul_rn(a.cD, div));
+    const double uxx = (ux[ce] - ux[cw]) / twodx;
+    const double uxy = (ux[cn] - ux[cs]) / twody;
+    const double uyx = (uy[ce] - uy[cw]) / twodx;
+    const double uyy = (uy[cn] - uy[cs]) / twody;
+    const double Tx = (T[ce] - T[cw]) / twodx;
+    const double Ty = (T[cn] - T[cs]) / twody;
+    const double div = uxx + uyy;
+    const double Dxx = (uxx + uxx) - a.cD * div;
+    const double Dxy = uxy + uyx;
+    const double Dyy = (uyy + uyy) - a.cD * div;
     const double e = a.eps[cell];
-    const double cv = __ddiv_rn(e, __dmul_rn(a.tau, a.omb));
-    const double ke = __dmul_rn(a.ck, e);
-    const double kt2 = __dmul_rn(a.cS, __ddiv_rn(__dmul_rn(ke, ke), __dmul_rn(__dmul_rn(a.tau, a.tau), T[cell])));
-    const double a11 = __dsub_rn(-__dmul_rn(cv, Dxx), __dmul_rn(kt2, __dmul_rn(Tx, Tx)));
-    const double a12 = __dsub_rn(-__dmul_rn(cv, Dxy), __dmul_rn(kt2, __dmul_rn(Tx, Ty)));
-    const double a22 = __dsub_rn(-__dmul_rn(cv, Dyy), __dmul_rn(kt2, __dmul_rn(Ty, Ty)));
-    const double m = __ddiv_rn(__dadd_rn(a11, a22), 2.0);
-    const double h = __ddiv_rn(__dsub_rn(a11, a22), 2.0);
-    const double q = __dadd_rn(__dmul_rn(h, h), __dmul_rn(a12, a12));
+    const double cv = e / (a.tau * a.omb);
+    const double ke = a.ck * e;
+    const double kt2 = a.cS * ((ke * ke) / ((a.tau * a.tau) * T[cell]));
+    const double a11 = -(cv * Dxx) - kt2 * (Tx * Tx);
+    const double a12 = -(cv * Dxy) - kt2 * (Tx * Ty);
+    const double a22 = -(cv * Dyy) - kt2 * (Ty * Ty);
+    const double m = (a11 + a22) / 2.0;
+    const double h = (a11 - a22) / 2.0;
+    const double q = h * h + a12 * a12;
     if (lam_out) *lam_out = fabs(m) + sqrt(q);  // report only
     // |m| + sqrt(q) > eta  <=>  eta - |m| < 0  or  q > (eta - |m|)^2: no square root decides
-    const double dd = __dsub_rn(a.eta, fabs(m));
-    const bool critS = (dd < 0.0) || (q > __dmul_rn(dd, dd));
+    const double dd = a.eta - fabs(m);
+    const bool critS = (dd < 0.0) || (q > dd * dd);
     const bool critL = a.l1[cell] > a.delta;
     return (uint8_t)(critS || (a.mask_old[cell] && critL));
 }

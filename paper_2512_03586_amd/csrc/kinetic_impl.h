@@ -163,10 +163,10 @@ struct GroupCell {
     bool valid;
 };
 
-template <int L> __device__ inline GroupCell group_cell(const int *list, int count) {
+template <int L, int WPB = 4> __device__ inline GroupCell group_cell(const int *list, int count) {
     constexpr int G = 64 / L;
     GroupCell gc{-1, false};
-    const int first = block_first_item(count, 4 * G);
+    const int first = block_first_item(count, WPB * G);
     if (first < 0) return gc;
     const int wave_first = first + (int)(threadIdx.x >> 6) * G;
     if (wave_first >= count) return gc;
@@ -212,48 +212,6 @@ __device__ inline Chunk<T> chunk_of(int s, int m, const Geom &g) {
 #pragma unroll
     for (int e = 0; e < 4; ++e) ch.vx[e] = v0 + (T)(ia + e) * dv;
     return ch;
-}
-
-// The 15 unscaled discrete moments S_pq = sum exp2(Q) a^p b^q (p + q <= 4) of a
-// sampled Gaussian over the group's nodes (weight and prefactor are applied by
-// the caller); the six of order <= 2 are compensated.  Order of S:
-// 00 10 01 20 11 02 30 21 12 03 40 31 22 13 04.
-template <class T, int L, int C, int NV>
-__device__ inline void gram_sums(const GaussEval<T> &ge, int s, const Geom &g, double S[15]) {
-    Comp<T> lowc[6];
-    T low[6] = {0, 0, 0, 0, 0, 0};
-    T high[9] = {0, 0, 0, 0, 0, 0, 0, 0, 0};
-#pragma unroll
-    for (int m = 0; m < C; ++m) {
-        const Chunk<T> ch = chunk_of<T, L, NV>(s, m, g);
-        if (ch.active) {
-            GaussRow<T> gr;
-            gr.set(ge, ch.vy);
-            const T b = (ch.vy - ge.uy) * ge.ist;
-            T p[5] = {0, 0, 0, 0, 0};
-#pragma unroll
-            for (int e = 0; e < 4; ++e) {
-                const T G = gr.tilde(ge, ch.vx[e]);
-                const T a = (ch.vx[e] - ge.ux) * ge.ist;
-                const T Ga = G * a, Ga2 = Ga * a, Ga3 = Ga2 * a;
-                p[0] += G; p[1] += Ga; p[2] += Ga2; p[3] += Ga3; p[4] += Ga3 * a;
-            }
-            const T b2 = b * b, b3 = b2 * b, b4 = b2 * b2;
-            low[0] += p[0]; low[1] += p[1]; low[2] += b * p[0];
-            low[3] += p[2]; low[4] += b * p[1]; low[5] += b2 * p[0];
-            high[0] += p[3]; high[1] += b * p[2]; high[2] += b2 * p[1]; high[3] += b3 * p[0];
-            high[4] += p[4]; high[5] += b * p[3]; high[6] += b2 * p[2]; high[7] += b3 * p[1];
-            high[8] += b4 * p[0];
-        }
-        if ((m & 3) == 3 || m == C - 1) {
-#pragma unroll
-            for (int q = 0; q < 6; ++q) { lowc[q].add(low[q]); low[q] = 0; }
-        }
-    }
-#pragma unroll
-    for (int q = 0; q < 6; ++q) S[q] = group_sum_comp<L>(lowc[q]);
-#pragma unroll
-    for (int q = 0; q < 9; ++q) S[6 + q] = (double)group_sum<L>(high[q]);
 }
 
 // Group-wide moments of the values v: compensated sums of f, v f and the raw
@@ -323,34 +281,6 @@ __device__ inline double group_l1(const T v[C][4], int s, const Geom &g, double 
     return g.w * (double)group_sum<L>(l1);
 }
 
-// FP64 Gaussian parameters of the relaxed state and its conservation
-// correction; returns the error bits.
-template <class T, int L, int C, int NV>
-__device__ inline int relaxed_gaussian(const double mo[7], double lam, int s, const Geom &g, double gp[GP_N]) {
-    const double beta = g.beta;
-    const double rho = mo[0], ux = mo[1], uy = mo[2], Tm = mo[3];
-    const double k = lam * (1.0 - beta);
-    const double ik = 1.0 / (1.0 + k);
-    const double thxx = (mo[4] + k * Tm) * ik;
-    const double thxy = mo[5] * ik;
-    const double thyy = (mo[6] + k * Tm) * ik;
-    const double txx = (1.0 - beta) * Tm + beta * thxx;
-    const double txy = beta * thxy;
-    const double tyy = (1.0 - beta) * Tm + beta * thyy;
-    int err = 0;
-    if (!gauss_params(rho, ux, uy, Tm, txx, txy, tyy, gp)) err |= ERR_SPD;
-    if (g.correction) {
-        GaussEval<T> ge;
-        ge.load(gp);
-        double S[15];
-        gram_sums<T, L, C, NV>(ge, s, g, S);
-#pragma unroll
-        for (int q = 0; q < 15; ++q) S[q] *= g.w;
-        if (!solve_correction(S, rho, Tm, txx, txy, tyy, gp)) err |= ERR_SPD;
-    }
-    return err;
-}
-
 // Moment partial sums of one chunk of values v into part[6] (sum f, vx f,
 // vy f, vx^2 f, vx vy f, vy^2 f), folded into the compensated lane sums every
 // 4 chunks.
@@ -396,16 +326,125 @@ template <class T> struct MomentAcc {
 // Per-lane staging of the explicit stage values f* in LDS between the
 // explicit pass and the relaxation: each lane writes and reads back only its
 // own 16-byte (FP32) slots, so no barrier is needed.
+// Waves per block: 4, or 1 when a wave's LDS staging is large (C > 9).
+template <int C> __host__ __device__ constexpr int waves_per_block() { return C > 9 ? 1 : 4; }
+
 template <class T, int C> struct StageLds {
-    T v[4][C][64][4];  // [wave in block][chunk][lane][node]
+    static constexpr int W = waves_per_block<C>();
+    T v[W][C][64][4];  // [wave in block][chunk][lane][node]: f*
+    T g[W][C][64][4];  // sampled Gaussian of the relaxed state
 };
 
+// The discrete-conservation correction of a sampled Gaussian (a reading: the
+// paper states exact conservation, Sec. 3.6).  With xi = (v-u)/sqrt(T),
+// psi = (1, a, b, a^2, ab, b^2), the corrected Gaussian is
+//   Ghat = Gtilde (1 + dc . psi)
+// with dc chosen so that Ghat's discrete moments of psi equal the continuous
+// ones t = (rho, 0, 0, rho Tt/T).  Pass 1 (gaussian_pass) evaluates Gtilde at
+// every node into LDS and accumulates its six discrete moments of order <= 2
+// (compensated); r = t - those.  When |r|/rho is below tol the moment matrix is
+// replaced by the continuous Gaussian's (closed form, residual second order in
+// the quadrature error); otherwise the nine higher discrete moments are summed
+// from LDS and the exact discrete Gram matrix is solved.  Returns error bits.
+template <class T, int L, int C, int NV>
+__device__ inline int correction_coeffs(const T (&glds)[C][64][4], int s, int lane, const Geom &g,
+                                        const GaussEval<T> &ge, const double Slow[6], double rho, double Tm,
+                                        double txx, double txy, double tyy, double tol, double dc[6]) {
+    const double iT = 1.0 / Tm;
+    double r[6];
+    r[0] = rho - Slow[0];
+    r[1] = -Slow[1];
+    r[2] = -Slow[2];
+    r[3] = rho * txx * iT - Slow[3];
+    r[4] = rho * txy * iT - Slow[4];
+    r[5] = rho * tyy * iT - Slow[5];
+    double rmax = 0.0;
+#pragma unroll
+    for (int q = 0; q < 6; ++q) rmax = fmax(rmax, fabs(r[q]));
+    if (rmax <= tol * rho) {
+        const double irho = 1.0 / rho;
+        double rr[6];
+#pragma unroll
+        for (int q = 0; q < 6; ++q) rr[q] = r[q] * irho;
+        solve_correction_gaussian(rr, txx * iT, txy * iT, tyy * iT, dc);
+        return 0;
+    }
+    // exact path: moments of order 3 and 4 of the stored Gaussian
+    T high[9] = {0, 0, 0, 0, 0, 0, 0, 0, 0};
+#pragma unroll
+    for (int m = 0; m < C; ++m) {
+        const Chunk<T> ch = chunk_of<T, L, NV>(s, m, g);
+        if (ch.active) {
+            const T b = (ch.vy - ge.uy) * ge.ist;
+            T p[5] = {0, 0, 0, 0, 0};
+#pragma unroll
+            for (int e = 0; e < 4; ++e) {
+                const T G = glds[m][lane][e];
+                const T a = (ch.vx[e] - ge.ux) * ge.ist;
+                const T Ga = G * a, Ga2 = Ga * a, Ga3 = Ga2 * a;
+                p[0] += G; p[1] += Ga; p[2] += Ga2; p[3] += Ga3; p[4] += Ga3 * a;
+            }
+            const T b2 = b * b, b3 = b2 * b, b4 = b2 * b2;
+            high[0] += p[3]; high[1] += b * p[2]; high[2] += b2 * p[1]; high[3] += b3 * p[0];
+            high[4] += p[4]; high[5] += b * p[3]; high[6] += b2 * p[2]; high[7] += b3 * p[1];
+            high[8] += b4 * p[0];
+        }
+    }
+    double S[15];
+#pragma unroll
+    for (int q = 0; q < 6; ++q) S[q] = Slow[q];
+#pragma unroll
+    for (int q = 0; q < 9; ++q) S[6 + q] = g.w * (double)group_sum<L>(high[q]);
+    return solve_correction_gram(S, r, dc) ? 0 : ERR_SPD;
+}
+
+// Pass 1 over the nodes for the Gaussian with parameters ge (prefactor pref):
+// Gtilde into glds, the six compensated discrete moments of order <= 2 into
+// Slow, and (when vlds is given) v <- (v + lam Gtilde) * inv1 in place.
+template <class T, int L, int C, int NV>
+__device__ inline void gaussian_pass(T (&glds)[C][64][4], T (*vlds)[64][4], int s, int lane, const Geom &g,
+                                     const GaussEval<T> &ge, T pref, T lam, T inv1, double Slow[6]) {
+    Comp<T> lowc[6];
+    T low[6] = {0, 0, 0, 0, 0, 0};
+#pragma unroll
+    for (int m = 0; m < C; ++m) {
+        const Chunk<T> ch = chunk_of<T, L, NV>(s, m, g);
+        if (ch.active) {
+            GaussRow<T> gr;
+            gr.set(ge, ch.vy);
+            const T b = (ch.vy - ge.uy) * ge.ist;
+            T p0 = 0, p1 = 0, p2 = 0;
+#pragma unroll
+            for (int e = 0; e < 4; ++e) {
+                const T G = pref * gr.tilde(ge, ch.vx[e]);
+                const T a = (ch.vx[e] - ge.ux) * ge.ist;
+                const T Ga = G * a;
+                p0 += G; p1 += Ga; p2 += Ga * a;
+                glds[m][lane][e] = G;
+                if (vlds) vlds[m][lane][e] = (vlds[m][lane][e] + lam * G) * inv1;
+            }
+            low[0] += p0; low[1] += p1; low[2] += b * p0;
+            low[3] += p2; low[4] += b * p1; low[5] += b * b * p0;
+        }
+        if ((m & 3) == 3 || m == C - 1) {
+#pragma unroll
+            for (int q = 0; q < 6; ++q) { lowc[q].add(low[q]); low[q] = 0; }
+        }
+    }
+#pragma unroll
+    for (int q = 0; q < 6; ++q) Slow[q] = g.w * group_sum_comp<L>(lowc[q]);
+}
+
+// Tolerance on |r|/rho for the closed-form correction: its residual is about
+// the square of the quadrature error, far below the arithmetic's rounding.
+template <class T> __device__ constexpr double correction_tol() { return sizeof(T) == 8 ? 1e-9 : 1e-6; }
+
 template <class S, int NV, int L, int C, int NL, int NQ, bool FINAL>
-__global__ __launch_bounds__(256, ESBGK_STAGE_MIN_WAVES) void stage_kernel(StageArgs<S> a) {
+__global__ __launch_bounds__(64 * waves_per_block<C>(), ESBGK_STAGE_MIN_WAVES) void stage_kernel(StageArgs<S> a) {
     using T = typename Storage<S>::T;
     __shared__ StageLds<T, C> lds;
     const Geom &g = a.g;
-    const GroupCell gc = group_cell<L>(a.list, *a.count);
+    const GroupCell gc = group_cell<L, waves_per_block<C>()>(a.list, *a.count);
     if (gc.cell < 0) return;
     const int cell = gc.cell;
     const int lane = (int)(threadIdx.x & 63), wave = (int)(threadIdx.x >> 6);
@@ -479,21 +518,44 @@ __global__ __launch_bounds__(256, ESBGK_STAGE_MIN_WAVES) void stage_kernel(Stage
     T l1 = 0;
 
     if constexpr (!FINAL) {
+        // ---- FP64 closed form of the implicit relaxation
         const double lam = g.dt * a.aii * te;
+        const double beta = g.beta;
+        const double k = lam * (1.0 - beta);
+        const double ik = 1.0 / (1.0 + k);
+        const double txx = (1.0 - beta) * Tm + beta * ((mo[4] + k * Tm) * ik);
+        const double txy = beta * (mo[5] * ik);
+        const double tyy = (1.0 - beta) * Tm + beta * ((mo[6] + k * Tm) * ik);
         double gp[GP_N];
-        errbits |= relaxed_gaussian<T, L, C, NV>(mo, lam, s, g, gp);
-        GaussEval<T> gi;
-        gi.load(gp);
+        if (!gauss_params(rho, ux, uy, Tm, txx, txy, tyy, gp)) errbits |= ERR_SPD;
+        GaussEval<T> ge;
+        ge.load(gp);
         const T lamt = (T)lam, inv1 = (T)(1.0 / (1.0 + lam));
+        // ---- Gaussian pass: Gtilde into LDS and its low-order discrete moments
+        double Slow[6];
+        gaussian_pass<T, L, C, NV>(lds.g[wave], nullptr, s, lane, g, ge, (T)gp[GP_PREF], lamt, inv1, Slow);
+        double dc[6] = {0, 0, 0, 0, 0, 0};
+        if (g.correction)
+            errbits |= correction_coeffs<T, L, C, NV>(lds.g[wave], s, lane, g, ge, Slow, rho, Tm, txx, txy, tyy,
+                                                      correction_tol<T>(), dc);
+        const double pref = gp[GP_PREF];
+#pragma unroll
+        for (int q = 0; q < 6; ++q) gp[GP_C0 + q] = pref * ((q == 0 ? 1.0 : 0.0) + dc[q]);
+        // ---- relaxation: f = (f* + lam Gtilde (1 + dc . psi)) / (1 + lam), the stage's single write
+        const T d0 = (T)dc[0], d1 = (T)dc[1], d2 = (T)dc[2], d3 = (T)dc[3], d4 = (T)dc[4], d5 = (T)dc[5];
 #pragma unroll
         for (int m = 0; m < C; ++m) {
             const Chunk<T> ch = chunk_of<T, L, NV>(s, m, g);
             if (ch.active) {
-                GaussRow<T> gr;
-                gr.set(gi, ch.vy);
+                const T b = (ch.vy - ge.uy) * ge.ist;
+                const T plin = d1 + d4 * b, pconst = d0 + (d2 + d5 * b) * b;
                 T fv[4];
 #pragma unroll
-                for (int e = 0; e < 4; ++e) fv[e] = (lds.v[wave][m][lane][e] + lamt * gr.hat(gi, ch.vx[e])) * inv1;
+                for (int e = 0; e < 4; ++e) {
+                    const T aa = (ch.vx[e] - ge.ux) * ge.ist;
+                    const T Ghat = lds.g[wave][m][lane][e] * ((T)1 + ((d3 * aa + plin) * aa + pconst));
+                    fv[e] = (lds.v[wave][m][lane][e] + lamt * Ghat) * inv1;
+                }
                 if (gc.valid) Storage<S>::store4(a.fout, nb.c + ch.k0, fv);
                 if (want_l1) {
                     const T ey = ch.vy - uyt, qy = mq * ey * ey;
@@ -543,13 +605,15 @@ __global__ __launch_bounds__(256, ESBGK_STAGE_MIN_WAVES) void stage_kernel(Stage
 // f = Mhat(U) at the listed cells (eq. Coupling_FluKin): the corrected sampled
 // Maxwellian, i.e. the corrected Gaussian with Tt = T I.
 template <class S, int NV, int L, int C>
-__global__ __launch_bounds__(256) void fill_maxwellian_kernel(FillArgs<S> a) {
+__global__ __launch_bounds__(64 * waves_per_block<C>()) void fill_maxwellian_kernel(FillArgs<S> a) {
     using T = typename Storage<S>::T;
+    __shared__ T glds[waves_per_block<C>()][C][64][4];
     const Geom &g = a.g;
-    const GroupCell gc = group_cell<L>(a.list, *a.count);
+    const GroupCell gc = group_cell<L, waves_per_block<C>()>(a.list, *a.count);
     if (gc.cell < 0) return;
     const int cell = gc.cell;
-    const int s = (int)(threadIdx.x & (L - 1));
+    const int lane = (int)(threadIdx.x & 63), wave = (int)(threadIdx.x >> 6);
+    const int s = lane & (L - 1);
     const size_t nc = (size_t)a.nc;
     const double rho = a.U[cell];
     const double ux = a.U[nc + cell] / rho, uy = a.U[2 * nc + cell] / rho;
@@ -557,26 +621,28 @@ __global__ __launch_bounds__(256) void fill_maxwellian_kernel(FillArgs<S> a) {
     int errbits = 0;
     double gp[GP_N];
     if (!gauss_params(rho, ux, uy, Tm, Tm, 0.0, Tm, gp)) errbits |= ERR_SPD;
-    if (g.correction) {
-        GaussEval<T> ge;
-        ge.load(gp);
-        double Sm[15];
-        gram_sums<T, L, C, NV>(ge, s, g, Sm);
-#pragma unroll
-        for (int q = 0; q < 15; ++q) Sm[q] *= g.w;
-        if (!solve_correction(Sm, rho, Tm, Tm, 0.0, Tm, gp)) errbits |= ERR_SPD;
-    }
-    GaussEval<T> gi;
-    gi.load(gp);
+    GaussEval<T> ge;
+    ge.load(gp);
+    double Slow[6];
+    gaussian_pass<T, L, C, NV>(glds[wave], nullptr, s, lane, g, ge, (T)gp[GP_PREF], (T)0, (T)1, Slow);
+    double dc[6] = {0, 0, 0, 0, 0, 0};
+    if (g.correction)
+        errbits |= correction_coeffs<T, L, C, NV>(glds[wave], s, lane, g, ge, Slow, rho, Tm, Tm, 0.0, Tm,
+                                                  correction_tol<T>(), dc);
+    const T d0 = (T)dc[0], d1 = (T)dc[1], d2 = (T)dc[2], d3 = (T)dc[3], d4 = (T)dc[4], d5 = (T)dc[5];
 #pragma unroll
     for (int m = 0; m < C; ++m) {
         const Chunk<T> ch = chunk_of<T, L, NV>(s, m, g);
         if (ch.active && gc.valid) {
-            GaussRow<T> gr;
-            gr.set(gi, ch.vy);
+            const T b = (ch.vy - ge.uy) * ge.ist;
+            const T plin = d1 + d4 * b, pconst = d0 + (d2 + d5 * b) * b;
             T v[4];
 #pragma unroll
-            for (int e = 0; e < 4; ++e) v[e] = gr.hat(gi, ch.vx[e]);
+            for (int e = 0; e < 4; ++e) {
+                const T aa = (ch.vx[e] - ge.ux) * ge.ist;
+                const T G = glds[wave][m][lane][e];
+                v[e] = G + G * ((d3 * aa + plin) * aa + pconst);
+            }
             Storage<S>::store4(a.f, (size_t)cell * g.nv2 + ch.k0, v);
         }
     }
@@ -682,8 +748,9 @@ static hipError_t stage_dispatch(const StageArgs<S> &a, int nmax, hipStream_t st
     const Shape sh = shape_for(a.g.nv2);
 #define ESBGK_CASE(NN, LL, CC)                                                                                     \
     if ((NN == 0) ? (sh.L == LL && sh.C == CC) : (a.g.nv == NN)) {                                                    \
-        hipLaunchKernelGGL((stage_kernel<S, NN, LL, CC, NL, NQ, FINAL>), dim3(grid_for(nmax, 4 * (64 / LL))),       \
-                           dim3(256), 0, st, a);                                                                    \
+        constexpr int WPB = waves_per_block<CC>();                                                                  \
+        hipLaunchKernelGGL((stage_kernel<S, NN, LL, CC, NL, NQ, FINAL>), dim3(grid_for(nmax, WPB * (64 / LL))),     \
+                           dim3(64 * WPB), 0, st, a);                                                               \
         return hipGetLastError();                                                                                   \
     }
     ESBGK_STATIC_NV(ESBGK_CASE)
@@ -709,8 +776,9 @@ hipError_t launch_fill(const FillArgs<S> &a, int nmax, hipStream_t st) {
     const Shape sh = shape_for(a.g.nv2);
 #define ESBGK_CASE(NN, LL, CC)                                                                               \
     if ((NN == 0) ? (sh.L == LL && sh.C == CC) : (a.g.nv == NN)) {                                              \
-        hipLaunchKernelGGL((fill_maxwellian_kernel<S, NN, LL, CC>), dim3(grid_for(nmax, 4 * (64 / LL))),      \
-                           dim3(256), 0, st, a);                                                              \
+        constexpr int WPB = waves_per_block<CC>();                                                            \
+        hipLaunchKernelGGL((fill_maxwellian_kernel<S, NN, LL, CC>), dim3(grid_for(nmax, WPB * (64 / LL))),    \
+                           dim3(64 * WPB), 0, st, a);                                                         \
         return hipGetLastError();                                                                             \
     }
     ESBGK_STATIC_NV(ESBGK_CASE)

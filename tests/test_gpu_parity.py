@@ -151,6 +151,8 @@ FP64_CASES = [
     (dict(nx=12, ny=10, nv=16, vmax=8.0, seed=2), 1, 1),
     (dict(nx=9, ny=11, nv=20, vmax=8.0, seed=3), 1, 1),
     (dict(nx=17, ny=8, nv=8, vmax=6.0, seed=4), 0, 1),
+    # resolved velocity grid (dv = 0.5): the correction takes its closed-form path
+    (dict(nx=10, ny=9, nv=32, vmax=8.0, seed=5), 1, 1),
 ]
 
 
@@ -213,7 +215,7 @@ def test_fully_kinetic_fp64_conserves():
 
 # ------------------------------------------------------------ FP32 / BF16
 
-@pytest.mark.parametrize("gen,scheme,recon", FP64_CASES[1:3])
+@pytest.mark.parametrize("gen,scheme,recon", FP64_CASES[1:3] + FP64_CASES[4:])
 def test_fully_kinetic_fp32_matches_oracle(gen, scheme, recon):
     d = inputs.riemann4(**gen)
     nc = d["nx"] * d["ny"]
