@@ -28,6 +28,7 @@ ROOT = os.path.dirname(os.path.abspath(__file__))
 sys.path.insert(0, ROOT)
 
 HBM_PEAK_GBS = 8000.0
+TRAFFIC_FILE = os.path.join(ROOT, "profiles", "traffic.json")
 
 WORKLOADS = {
     # name: (generator, kwargs, nx, nv, vmax, steps in the configuration)
@@ -40,6 +41,36 @@ WORKLOADS = {
 PASSES = {"stage2": 2, "stage3": 3, "final": 4}
 
 
+def kernel_source_digest():
+    """sha256 of the HIP sources: a recorded traffic figure holds only for the
+    kernels it was measured on."""
+    import hashlib
+    csrc = os.path.join(ROOT, "paper_2512_03586_amd", "csrc")
+    h = hashlib.sha256()
+    for name in sorted(os.listdir(csrc)):
+        if name.endswith((".h", ".hip")):
+            with open(os.path.join(csrc, name), "rb") as fh:
+                h.update(name.encode() + b"\0" + fh.read())
+    return h.hexdigest()
+
+
+def recorded_traffic(kernel, workload, precision, steps):
+    """HBM bytes per launch of `kernel` from the committed rocprofv3 FETCH_SIZE /
+    WRITE_SIZE summary of this same command, or None when the kernel sources,
+    the workload or the step count differ from the profiled run."""
+    try:
+        with open(TRAFFIC_FILE) as fh:
+            rec = json.load(fh)
+    except (OSError, ValueError):
+        return None
+    if rec.get("source_sha256") != kernel_source_digest():
+        return None
+    e = rec.get("kernels", {}).get(kernel)
+    if not e or rec.get("workload") != workload or rec.get("precision") != precision or rec.get("steps") != steps:
+        return None
+    return e["fetch_bytes_per_launch"] + e["write_bytes_per_launch"]
+
+
 def parse():
     ap = argparse.ArgumentParser()
     ap.add_argument("--gpus", type=int, default=1)
@@ -48,7 +79,7 @@ def parse():
     ap.add_argument("--precision", default="fp32", choices=["fp32", "bf16", "fp64"])
     ap.add_argument("--workload", default="riemann4", choices=sorted(WORKLOADS))
     ap.add_argument("--no-cpu-baseline", action="store_true")
-    ap.add_argument("--cpu-steps", type=int, default=8)
+    ap.add_argument("--cpu-steps", type=int, default=16)
     ap.add_argument("--calibrate-copy", type=int, default=0, metavar="MIB",
                     help="first run one plain device-to-device tensor copy of MIB MiB (a kernel of "
                          "known traffic, to scale HBM byte counters)")
@@ -57,14 +88,15 @@ def parse():
 
 def cpu_baseline(wl, nsteps):
     """The FP64 oracle, as it stands, on a bounded sample of the same workload:
-    the same generator and physics on a 128 x 128 spatial grid with the full
-    velocity grid, a few steps with the regime update on."""
+    the same generator, grid and physics, the first `nsteps` steps after one
+    warm-up step (the kinetic region is still small then, so the sample holds
+    fewer kinetic cells per step than the timed GPU run)."""
     import numpy as np
 
     import oracle
     from paper_2512_03586_amd import inputs
     oracle.build(force=False)
-    nx = 128
+    nx = wl["nx"]
     d = getattr(inputs, wl["gen"])(nx=nx, ny=nx, nv=wl["nv"], vmax=wl["vmax"], **wl["kw"])
     p = oracle.Problem(nx=nx, ny=nx, nv=wl["nv"], vmax=wl["vmax"], scheme=1, recon=1, eta=1e-2, delta=1e-3)
     st = oracle.State.from_primitives(p, d["rho"], d["ux"], d["uy"], d["T"], d["eps"])
@@ -161,7 +193,8 @@ def main():
                    "kinetic_cells_per_step": round(kin_avg, 1),
                    "kernel_ms_per_launch": breakdown},
         "roofline": {"bound": "hbm", "kernel": names[dom], "achieved": achieved, "peak": HBM_PEAK_GBS,
-                     "unit": "GB/s", "frac": achieved / HBM_PEAK_GBS, "traffic": None,
+                     "unit": "GB/s", "frac": achieved / HBM_PEAK_GBS,
+                     "traffic": recorded_traffic(names[dom], args.workload, args.precision, args.steps),
                      "algorithmic_bytes_per_launch": bytes_launch},
     }
     if stats.error_flags:
