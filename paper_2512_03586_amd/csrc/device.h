@@ -30,12 +30,12 @@ template <class S> struct Storage;
 
 template <> struct Storage<double> {
     using T = double;  // arithmetic type
-    __device__ static inline void load4(const double *p, size_t idx, double v[4]) {
+    template <class I> __device__ static inline void load4(const double *p, I idx, double v[4]) {
         const double2 *q = reinterpret_cast<const double2 *>(p + idx);
         double2 a = q[0], b = q[1];
         v[0] = a.x; v[1] = a.y; v[2] = b.x; v[3] = b.y;
     }
-    __device__ static inline void store4(double *p, size_t idx, const double v[4]) {
+    template <class I> __device__ static inline void store4(double *p, I idx, const double v[4]) {
         double2 *q = reinterpret_cast<double2 *>(p + idx);
         q[0] = make_double2(v[0], v[1]);
         q[1] = make_double2(v[2], v[3]);
@@ -44,11 +44,11 @@ template <> struct Storage<double> {
 
 template <> struct Storage<float> {
     using T = float;
-    __device__ static inline void load4(const float *p, size_t idx, float v[4]) {
+    template <class I> __device__ static inline void load4(const float *p, I idx, float v[4]) {
         float4 a = *reinterpret_cast<const float4 *>(p + idx);
         v[0] = a.x; v[1] = a.y; v[2] = a.z; v[3] = a.w;
     }
-    __device__ static inline void store4(float *p, size_t idx, const float v[4]) {
+    template <class I> __device__ static inline void store4(float *p, I idx, const float v[4]) {
         *reinterpret_cast<float4 *>(p + idx) = make_float4(v[0], v[1], v[2], v[3]);
     }
 };
@@ -62,12 +62,12 @@ __device__ inline uint32_t f32_to_bf16(float f) {
 
 template <> struct Storage<bf16_t> {
     using T = float;
-    __device__ static inline void load4(const bf16_t *p, size_t idx, float v[4]) {
+    template <class I> __device__ static inline void load4(const bf16_t *p, I idx, float v[4]) {
         uint2 a = *reinterpret_cast<const uint2 *>(p + idx);
         v[0] = __uint_as_float(a.x << 16); v[1] = __uint_as_float(a.x & 0xFFFF0000u);
         v[2] = __uint_as_float(a.y << 16); v[3] = __uint_as_float(a.y & 0xFFFF0000u);
     }
-    __device__ static inline void store4(bf16_t *p, size_t idx, const float v[4]) {
+    template <class I> __device__ static inline void store4(bf16_t *p, I idx, const float v[4]) {
         uint2 a;
         a.x = f32_to_bf16(v[0]) | (f32_to_bf16(v[1]) << 16);
         a.y = f32_to_bf16(v[2]) | (f32_to_bf16(v[3]) << 16);
@@ -157,21 +157,33 @@ template <class T> struct Comp {
     __device__ inline double value() const { return (double)hi + (double)lo; }
 };
 
+#ifndef ESBGK_COMP_BUTTERFLY
+#define ESBGK_COMP_BUTTERFLY 0
+#endif
+
+// Group total of compensated lane partials.  Default: each lane's (hi + lo) is
+// formed in FP64 and the butterfly adds in FP64 (about 64 * 2^-53 relative
+// error, far below the FP32 partials' own), a third of the instructions of a
+// butterfly of TwoSum merges.
 template <int L, class T> __device__ inline double group_sum_comp(Comp<T> c) {
-    c.merge(partner<0>(c.hi), partner<0>(c.lo));
-    c.merge(partner<1>(c.hi), partner<1>(c.lo));
-    c.merge(partner<2>(c.hi), partner<2>(c.lo));
-    c.merge(partner<3>(c.hi), partner<3>(c.lo));
-    if constexpr (L >= 32) c.merge(partner<4>(c.hi), partner<4>(c.lo));
-    if constexpr (L == 64) {
-        T h0 = readlane(c.hi, 0), l0 = readlane(c.lo, 0);
-        T h1 = readlane(c.hi, 32), l1 = readlane(c.lo, 32);
-        Comp<T> r;
-        r.hi = h0; r.lo = l0;
-        r.merge(h1, l1);
-        return r.value();
+    if constexpr (ESBGK_COMP_BUTTERFLY == 0) {
+        return group_sum<L>((double)c.hi + (double)c.lo);
+    } else {
+        c.merge(partner<0>(c.hi), partner<0>(c.lo));
+        c.merge(partner<1>(c.hi), partner<1>(c.lo));
+        c.merge(partner<2>(c.hi), partner<2>(c.lo));
+        c.merge(partner<3>(c.hi), partner<3>(c.lo));
+        if constexpr (L >= 32) c.merge(partner<4>(c.hi), partner<4>(c.lo));
+        if constexpr (L == 64) {
+            T h0 = readlane(c.hi, 0), l0 = readlane(c.lo, 0);
+            T h1 = readlane(c.hi, 32), l1 = readlane(c.lo, 32);
+            Comp<T> r;
+            r.hi = h0; r.lo = l0;
+            r.merge(h1, l1);
+            return r.value();
+        }
+        return c.value();
     }
-    return c.value();
 }
 
 // -------------------------------------------------------- kernel geometry
@@ -179,6 +191,7 @@ template <int L, class T> __device__ inline double group_sum_comp(Comp<T> c) {
 struct Geom {
     int nx, ny, nv, nv2;
     double dx, dy, dv, vmax, w;  // w = dv^2 quadrature weight
+    double idx, idy;             // 1/dx, 1/dy
     double beta, tau, dt;
     int recon, correction;
 };

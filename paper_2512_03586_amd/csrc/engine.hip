@@ -278,7 +278,7 @@ template <class S> int run_step(esbgk_ctx *c, hipStream_t st) {
     // ---- regime update (Algorithm 1: at the start of every step)
     if (c->cfg.indicator == ESBGK_IND_PLAIN) {
         HIPCHK(launch_prim(c->U[0], c->prim, c->nc, st));
-        HIPCHK(hipMemcpyAsync(c->mask_old, c->mask, nc, hipMemcpyDeviceToDevice, st));
+        std::swap(c->mask_old, c->mask);  // the indicator writes the new mask from the previous one
         IndicatorArgs ia = indicator_args(&c->cfg);
         ia.prim = c->prim; ia.eps = c->eps; ia.l1 = c->l1; ia.mask_old = c->mask_old; ia.mask_new = c->mask;
         HIPCHK(launch_indicator(ia, st));
@@ -373,6 +373,7 @@ int esbgk_create(const esbgk_config *cfg, void *d_workspace, size_t bytes, esbgk
     Geom &g = c->g;
     g.nx = cfg->nx; g.ny = cfg->ny; g.nv = cfg->nv; g.nv2 = c->nv2;
     g.dx = cfg->lx / cfg->nx; g.dy = cfg->ly / cfg->ny;
+    g.idx = 1.0 / g.dx; g.idy = 1.0 / g.dy;
     g.vmax = cfg->vmax;
     g.dv = 2.0 * cfg->vmax / (double)cfg->nv;
     g.w = g.dv * g.dv;

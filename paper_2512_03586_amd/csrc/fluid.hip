@@ -3,11 +3,6 @@
 // and the deterministic stream compaction of kinetic / buffer cells.
 #include "kernels.h"
 
-// Every floating-point expression in this file is evaluated as written: no
-// fused multiply-add contraction (the indicator's results must be the
-// correctly rounded IEEE operations of its documented order).
-#pragma clang fp contract(off)
-
 namespace esbgk {
 
 __device__ inline int wrapc(int i, int n) { i %= n; return i < 0 ? i + n : i; }
@@ -32,14 +27,14 @@ __device__ inline void euler_flux(const double U[4], int d, double F[4], double 
     *speed = fabs(un) + sqrt(2.0 * P / rho);
 }
 
-// Rusanov flux at the face between cells p and q (Sec. 3.2, Lax-Friedrichs
-// type), reconstruction applied component-wise to U.
-__device__ inline void euler_face(const double *U, size_t nc, size_t cpm, size_t cp, size_t cq,
-                                  size_t cqp, int d, int recon, double Fh[4]) {
+// Rusanov flux (Sec. 3.2, Lax-Friedrichs type) at the face between stencil
+// cells 1 and 2 of st[q][0..3] (the 4 cells along direction d), with the
+// kinetic transport's reconstruction applied component-wise to U.
+__device__ inline void euler_face_vals(const double st[4][4], int d, int recon, double Fh[4]) {
     double UL[4], UR[4];
 #pragma unroll
     for (int q = 0; q < 4; ++q) {
-        double a = U[q * nc + cpm], b = U[q * nc + cp], e = U[q * nc + cq], g = U[q * nc + cqp];
+        const double a = st[q][0], b = st[q][1], e = st[q][2], g = st[q][3];
         double sp = 0.0, sq = 0.0;
         if (recon == 1) {
             sp = dminmod(b - a, e - b);
@@ -51,37 +46,90 @@ __device__ inline void euler_face(const double *U, size_t nc, size_t cpm, size_t
     double FL[4], FR[4], aL, aR;
     euler_flux(UL, d, FL, &aL);
     euler_flux(UR, d, FR, &aR);
-    double s = fmax(aL, aR);
+    const double s = fmax(aL, aR);
 #pragma unroll
     for (int q = 0; q < 4; ++q) Fh[q] = 0.5 * (FL[q] + FR[q]) - 0.5 * s * (UR[q] - UL[q]);
 }
 
 // U^(i) = U^n - dt sum_j c_j Phi(U^(j)) on fluid cells (eqs. RKEuler, RKEuler_2).
-__global__ void euler_stage_kernel(EulerArgs a) {
-    const int cell = blockIdx.x * blockDim.x + threadIdx.x;
-    if (cell >= a.nc) return;
-    if (a.mask[cell]) return;
-    const size_t nc = (size_t)a.nc;
+// One 16 x 16 tile of cells per block: each U^(j) tile with its 2-cell
+// periodic halo is staged in LDS, every face flux of the tile is computed once
+// (17 x 16 faces per direction), and each cell takes the difference of its two
+// faces per direction.
+constexpr int ET = 16, EH = 2, EW = ET + 2 * EH;
+
+__global__ __launch_bounds__(ET * ET) void euler_stage_kernel(EulerArgs a) {
+    __shared__ double u[4][EW][EW];
+    __shared__ double fx[4][ET][ET + 1];
+    __shared__ double fy[4][ET + 1][ET];
+    const int tx = (int)threadIdx.x % ET, ty = (int)threadIdx.x / ET, tid = (int)threadIdx.x;
+    const int i0 = (int)blockIdx.x * ET, j0 = (int)blockIdx.y * ET;
     const int nx = a.nx, ny = a.ny;
-    const int i = cell % nx, j = cell / nx;
-    auto CI = [&](int ii, int jj) { return (size_t)wrapc(jj, ny) * nx + wrapc(ii, nx); };
-    double s[4];
+    const size_t nc = (size_t)a.nc;
+    const int i = i0 + tx, j = j0 + ty;
+    const bool own = i < nx && j < ny;
+    const size_t cell = own ? (size_t)j * nx + i : 0;
+    const bool fluid = own && !a.mask[cell];
+    if (!__syncthreads_or(fluid)) return;  // whole tile kinetic (or outside)
+    double s[4] = {0, 0, 0, 0};
+    if (fluid) {
 #pragma unroll
-    for (int q = 0; q < 4; ++q) s[q] = a.Un[q * nc + cell];
+        for (int q = 0; q < 4; ++q) s[q] = a.Un[q * nc + cell];
+    }
     for (int jj = 0; jj < a.nj; ++jj) {
         const double *U = a.Uj[jj];
-        double Fp[4], Fm[4], Gp[4], Gm[4];
-        euler_face(U, nc, CI(i - 1, j), CI(i, j), CI(i + 1, j), CI(i + 2, j), 0, a.recon, Fp);
-        euler_face(U, nc, CI(i - 2, j), CI(i - 1, j), CI(i, j), CI(i + 1, j), 0, a.recon, Fm);
-        euler_face(U, nc, CI(i, j - 1), CI(i, j), CI(i, j + 1), CI(i, j + 2), 1, a.recon, Gp);
-        euler_face(U, nc, CI(i, j - 2), CI(i, j - 1), CI(i, j), CI(i, j + 1), 1, a.recon, Gm);
+        for (int t = tid; t < EW * EW; t += ET * ET) {
+            const int li = t % EW, lj = t / EW;
+            const int gi = wrapc(i0 + li - EH, nx), gj = wrapc(j0 + lj - EH, ny);
+            const size_t c = (size_t)gj * nx + gi;
+#pragma unroll
+            for (int q = 0; q < 4; ++q) u[q][lj][li] = U[q * nc + c];
+        }
+        __syncthreads();
+        // x-face f (0..16) of row r lies between local cells f-1 and f
+        for (int t = tid; t < ET * (ET + 1); t += ET * ET) {
+            const int r = t / (ET + 1), f = t % (ET + 1);
+            const int y = r + EH, x = f + EH;
+            double st[4][4], F[4];
+#pragma unroll
+            for (int q = 0; q < 4; ++q) {
+                st[q][0] = u[q][y][x - 2]; st[q][1] = u[q][y][x - 1];
+                st[q][2] = u[q][y][x]; st[q][3] = u[q][y][x + 1];
+            }
+            euler_face_vals(st, 0, a.recon, F);
+#pragma unroll
+            for (int q = 0; q < 4; ++q) fx[q][r][f] = F[q];
+        }
+        for (int t = tid; t < ET * (ET + 1); t += ET * ET) {
+            const int f = t / ET, cidx = t % ET;
+            const int y = f + EH, x = cidx + EH;
+            double st[4][4], F[4];
+#pragma unroll
+            for (int q = 0; q < 4; ++q) {
+                st[q][0] = u[q][y - 2][x]; st[q][1] = u[q][y - 1][x];
+                st[q][2] = u[q][y][x]; st[q][3] = u[q][y + 1][x];
+            }
+            euler_face_vals(st, 1, a.recon, F);
+#pragma unroll
+            for (int q = 0; q < 4; ++q) fy[q][f][cidx] = F[q];
+        }
+        __syncthreads();
         const double c = a.dt * a.cj[jj];
 #pragma unroll
-        for (int q = 0; q < 4; ++q) s[q] -= c * ((Fp[q] - Fm[q]) / a.dx + (Gp[q] - Gm[q]) / a.dy);
+        for (int q = 0; q < 4; ++q)
+            s[q] -= c * ((fx[q][ty][tx + 1] - fx[q][ty][tx]) / a.dx + (fy[q][ty + 1][tx] - fy[q][ty][tx]) / a.dy);
+        __syncthreads();
     }
+    if (fluid) {
 #pragma unroll
-    for (int q = 0; q < 4; ++q) a.Uout[q * nc + cell] = s[q];
+        for (int q = 0; q < 4; ++q) a.Uout[q * nc + cell] = s[q];
+    }
 }
+
+// Every floating-point expression from here on is evaluated as written: no
+// fused multiply-add contraction (the indicator's results must be the
+// correctly rounded IEEE operations of its documented order).
+#pragma clang fp contract(off)
 
 // ------------------------------------------------------- conversions
 
@@ -329,7 +377,8 @@ __global__ void accumulate_count_kernel(const int *counts, long long *total) {
 static inline unsigned cells_grid(int n) { return (unsigned)((n + 255) / 256 > 0 ? (n + 255) / 256 : 1); }
 
 hipError_t launch_euler(const EulerArgs &a, hipStream_t st) {
-    hipLaunchKernelGGL(euler_stage_kernel, dim3(cells_grid(a.nc)), dim3(256), 0, st, a);
+    const dim3 grid((unsigned)((a.nx + ET - 1) / ET), (unsigned)((a.ny + ET - 1) / ET));
+    hipLaunchKernelGGL(euler_stage_kernel, grid, dim3(ET * ET), 0, st, a);
     return hipGetLastError();
 }
 

@@ -21,6 +21,12 @@
 #pragma once
 #include "kernels.h"
 
+// implicit stages: stencil loads of the next work unit issued before the
+// current one is computed
+#ifndef ESBGK_PREFETCH
+#define ESBGK_PREFETCH 1
+#endif
+
 // waves per SIMD the stage kernels are compiled for (caps their VGPR budget)
 #ifndef ESBGK_STAGE_MIN_WAVES
 #define ESBGK_STAGE_MIN_WAVES 3
@@ -68,70 +74,77 @@ template <class T> struct Chunk {
     T vx[4], vy;
 };
 
-// |v_x| (F_{i+1/2} - F_{i-1/2}) / dx + |v_y| (G_{j+1/2} - G_{j-1/2}) / dy at the
-// 4 nodes of a chunk (the transport operator L), and the cell's own values fc.
-template <class S>
-__device__ inline void transport4(const S *f, const Nbr &nb, const Chunk<typename Storage<S>::T> &ch,
-                                  typename Storage<S>::T idx, typename Storage<S>::T idy, int recon,
-                                  typename Storage<S>::T fc[4], typename Storage<S>::T out[4]) {
-    using T = typename Storage<S>::T;
-    const int k0 = ch.k0;
-    Storage<S>::load4(f, nb.c + k0, fc);
-    // y: one velocity per chunk, pick the upwind / downwind / far neighbours
+// Stencil values of one chunk of one f array: the cell's own values c, the
+// y-neighbours upwind / downwind / far (y[0..2]) and the x-neighbours
+// (x[0..2] upwind / downwind / far; a chunk that straddles v_x = 0 holds
+// i-1, i+1, i-2, i+2 in x[0..3]).  RECON: 0 first-order upwind (only c, y[0],
+// x[0] or x[0..1]), 1 minmod-limited upwind.
+template <class T> struct Stencil {
+    T c[4], y[3][4], x[4][4];
+    T b[4];  // final combination: f^n at the cell, loaded with the chunk's first unit
+};
+
+// Issue the loads of a chunk's stencil.  The neighbour bases are wave-uniform
+// when a wavefront owns one cell, so each load is a scalar base plus a 32-bit
+// lane offset.
+template <class S, int RECON>
+__device__ inline void load_stencil(const S *f, const Nbr &nb, const Chunk<typename Storage<S>::T> &ch,
+                                    Stencil<typename Storage<S>::T> &st) {
+    const uint32_t k0 = (uint32_t)ch.k0;
     const bool ypos = ch.ypos;
-    const T avy = (ypos ? ch.vy : -ch.vy) * idy;
-    T yu[4];
-    Storage<S>::load4(f, (ypos ? nb.ym1 : nb.yp1) + k0, yu);
-    T Ly[4];
-    if (recon == 0) {
-#pragma unroll
-        for (int e = 0; e < 4; ++e) Ly[e] = avy * (fc[e] - yu[e]);
-    } else {
-        T yd[4], yf[4];
-        Storage<S>::load4(f, (ypos ? nb.yp1 : nb.ym1) + k0, yd);
-        Storage<S>::load4(f, (ypos ? nb.ym2 : nb.yp2) + k0, yf);
-#pragma unroll
-        for (int e = 0; e < 4; ++e) Ly[e] = avy * limited_diff(yf[e], yu[e], fc[e], yd[e]);
+    Storage<S>::load4(f + nb.c, k0, st.c);
+    Storage<S>::load4(f + (ypos ? nb.ym1 : nb.yp1), k0, st.y[0]);
+    if constexpr (RECON != 0) {
+        Storage<S>::load4(f + (ypos ? nb.yp1 : nb.ym1), k0, st.y[1]);
+        Storage<S>::load4(f + (ypos ? nb.ym2 : nb.yp2), k0, st.y[2]);
     }
-    // x: the 4 nodes of a chunk share the sign of v_x unless the chunk straddles 0
     if (!ch.straddle) {
         const bool pos = ch.xpos;
-        T xu[4];
-        Storage<S>::load4(f, (pos ? nb.xm1 : nb.xp1) + k0, xu);
-        if (recon == 0) {
-#pragma unroll
-            for (int e = 0; e < 4; ++e) {
-                const T avx = (pos ? ch.vx[e] : -ch.vx[e]) * idx;
-                out[e] = avx * (fc[e] - xu[e]) + Ly[e];
-            }
-        } else {
-            T xd[4], xf[4];
-            Storage<S>::load4(f, (pos ? nb.xp1 : nb.xm1) + k0, xd);
-            Storage<S>::load4(f, (pos ? nb.xm2 : nb.xp2) + k0, xf);
-#pragma unroll
-            for (int e = 0; e < 4; ++e) {
-                const T avx = (pos ? ch.vx[e] : -ch.vx[e]) * idx;
-                out[e] = avx * limited_diff(xf[e], xu[e], fc[e], xd[e]) + Ly[e];
-            }
+        Storage<S>::load4(f + (pos ? nb.xm1 : nb.xp1), k0, st.x[0]);
+        if constexpr (RECON != 0) {
+            Storage<S>::load4(f + (pos ? nb.xp1 : nb.xm1), k0, st.x[1]);
+            Storage<S>::load4(f + (pos ? nb.xm2 : nb.xp2), k0, st.x[2]);
         }
     } else {
-        // straddling chunk (nv not a multiple of 8): per-node selection
-        T xm1[4], xp1[4], xm2[4], xp2[4];
-        Storage<S>::load4(f, nb.xm1 + k0, xm1);
-        Storage<S>::load4(f, nb.xp1 + k0, xp1);
-        Storage<S>::load4(f, nb.xm2 + k0, xm2);
-        Storage<S>::load4(f, nb.xp2 + k0, xp2);
+        Storage<S>::load4(f + nb.xm1, k0, st.x[0]);
+        Storage<S>::load4(f + nb.xp1, k0, st.x[1]);
+        if constexpr (RECON != 0) {
+            Storage<S>::load4(f + nb.xm2, k0, st.x[2]);
+            Storage<S>::load4(f + nb.xp2, k0, st.x[3]);
+        }
+    }
+}
+
+// |v_x| (F_{i+1/2} - F_{i-1/2}) / dx + |v_y| (G_{j+1/2} - G_{j-1/2}) / dy at the
+// 4 nodes of a chunk: the transport operator L of Sec. 3.2 with upwind or
+// minmod-limited face values.
+template <class T, int RECON>
+__device__ inline void transport_of(const Stencil<T> &st, const Chunk<T> &ch, T idx, T idy, T out[4]) {
+    const T avy = (ch.ypos ? ch.vy : -ch.vy) * idy;
+    T Ly[4];
+#pragma unroll
+    for (int e = 0; e < 4; ++e)
+        Ly[e] = avy * (RECON == 0 ? st.c[e] - st.y[0][e] : limited_diff(st.y[2][e], st.y[0][e], st.c[e], st.y[1][e]));
+    if (!ch.straddle) {
+        const bool pos = ch.xpos;
+#pragma unroll
+        for (int e = 0; e < 4; ++e) {
+            const T avx = (pos ? ch.vx[e] : -ch.vx[e]) * idx;
+            out[e] = avx * (RECON == 0 ? st.c[e] - st.x[0][e]
+                                       : limited_diff(st.x[2][e], st.x[0][e], st.c[e], st.x[1][e])) + Ly[e];
+        }
+    } else {
 #pragma unroll
         for (int e = 0; e < 4; ++e) {
             const bool pos = ch.vx[e] > (T)0;
             const T avx = (pos ? ch.vx[e] : -ch.vx[e]) * idx;
-            const T up = pos ? xm1[e] : xp1[e];
-            if (recon == 0) {
-                out[e] = avx * (fc[e] - up) + Ly[e];
+            const T up = pos ? st.x[0][e] : st.x[1][e];
+            if constexpr (RECON == 0) {
+                out[e] = avx * (st.c[e] - up) + Ly[e];
             } else {
-                const T far = pos ? xm2[e] : xp2[e];
-                const T dn = pos ? xp1[e] : xm1[e];
-                out[e] = avx * limited_diff(far, up, fc[e], dn) + Ly[e];
+                const T far = pos ? st.x[2][e] : st.x[3][e];
+                const T dn = pos ? st.x[1][e] : st.x[0][e];
+                out[e] = avx * limited_diff(far, up, st.c[e], dn) + Ly[e];
             }
         }
     }
@@ -168,8 +181,14 @@ template <int L, int WPB = 4> __device__ inline GroupCell group_cell(const int *
     GroupCell gc{-1, false};
     const int first = block_first_item(count, WPB * G);
     if (first < 0) return gc;
-    const int wave_first = first + (int)(threadIdx.x >> 6) * G;
+    const int wave_first = first + __builtin_amdgcn_readfirstlane((int)(threadIdx.x >> 6)) * G;
     if (wave_first >= count) return gc;
+    if constexpr (L == 64) {
+        // one cell per wavefront: keep its index (and all neighbour arithmetic) scalar
+        gc.valid = true;
+        gc.cell = __builtin_amdgcn_readfirstlane(list[wave_first]);
+        return gc;
+    }
     int item = wave_first + (int)((threadIdx.x & 63) / L);
     gc.valid = item < count;
     if (!gc.valid) item = count - 1;
@@ -439,7 +458,7 @@ __device__ inline void gaussian_pass(T (&glds)[C][64][4], T (*vlds)[64][4], int 
 // the square of the quadrature error, far below the arithmetic's rounding.
 template <class T> __device__ constexpr double correction_tol() { return sizeof(T) == 8 ? 1e-9 : 1e-6; }
 
-template <class S, int NV, int L, int C, int NL, int NQ, bool FINAL>
+template <class S, int NV, int L, int C, int NL, int NQ, bool FINAL, int RECON>
 __global__ __launch_bounds__(64 * waves_per_block<C>(), ESBGK_STAGE_MIN_WAVES) void stage_kernel(StageArgs<S> a) {
     using T = typename Storage<S>::T;
     __shared__ StageLds<T, C> lds;
@@ -451,7 +470,7 @@ __global__ __launch_bounds__(64 * waves_per_block<C>(), ESBGK_STAGE_MIN_WAVES) v
     const int s = lane & (L - 1);
     const bool leader = gc.valid && s == 0;
     const Nbr nb = neighbours(cell, g);
-    const T idx = (T)(1.0 / g.dx), idy = (T)(1.0 / g.dy);
+    const T idx = (T)g.idx, idy = (T)g.idy;
     const double te = g.tau / a.eps[cell];
     const T dt = (T)g.dt, dtte = (T)(g.dt * te);
 
@@ -459,46 +478,72 @@ __global__ __launch_bounds__(64 * waves_per_block<C>(), ESBGK_STAGE_MIN_WAVES) v
 #pragma unroll
     for (int q = 0; q < NQ; ++q) gq[q].load(a.pq[q] + (size_t)cell * GP_N);
 
-    // ---- explicit part of the stage, moments on the fly
+    // ---- explicit part of the stage, moments on the fly.  Work unit u =
+    // (chunk m = u / NL, transported array l = u % NL); with prefetching the
+    // loads of unit u + 1 are in flight while unit u is computed.  The source
+    // arrays of the implicit terms are the last NQ transported arrays (the
+    // launcher checks this), so their values are the stencil centres.
     MomentAcc<T> macc;
-#pragma unroll
-    for (int m = 0; m < C; ++m) {
+    constexpr int NU = C * NL;
+    constexpr bool PF = ESBGK_PREFETCH != 0 && !FINAL;  // the final kernel would spill
+    constexpr int NB = PF ? 2 : 1;
+    Stencil<T> sb[NB];
+    T base[4], acc[4], qsum[4];  // base: f^n at the cell
+    auto load_unit = [&](int u, int slot) {
+        const int m = u / NL, l = u % NL;
         const Chunk<T> ch = chunk_of<T, L, NV>(s, m, g);
+        if (!ch.active) return;
+        load_stencil<S, RECON>(a.fl[l], nb, ch, sb[slot]);
+        if (FINAL && l == 0) Storage<S>::load4(a.fn + nb.c, (uint32_t)ch.k0, sb[slot].b);
+    };
+    if (PF) load_unit(0, 0);
+#pragma unroll
+    for (int u = 0; u < NU; ++u) {
+        const int m = u / NL, l = u % NL;
+        const int slot = PF ? (u & 1) : 0;
+        const Chunk<T> ch = chunk_of<T, L, NV>(s, m, g);
+        if (PF) {
+            if (u + 1 < NU) load_unit(u + 1, (u + 1) & 1);
+        } else {
+            load_unit(u, 0);
+        }
+        const Stencil<T> &cur = sb[slot];
         if (ch.active) {
-            T base[4], acc[4] = {0, 0, 0, 0}, fs[4];
+            T Lt[4];
+            transport_of<T, RECON>(cur, ch, idx, idy, Lt);
+            const T cl = (T)a.cl[l];
 #pragma unroll
-            for (int l = 0; l < NL; ++l) {
-                T fc[4], Lt[4];
-                transport4<S>(a.fl[l], nb, ch, idx, idy, g.recon, fc, Lt);
-                const T cl = (T)a.cl[l];
-#pragma unroll
-                for (int e = 0; e < 4; ++e) acc[e] += cl * Lt[e];
-                if (l == 0 && !FINAL) {
-#pragma unroll
-                    for (int e = 0; e < 4; ++e) base[e] = fc[e];  // the stages transport f^n first
-                }
+            for (int e = 0; e < 4; ++e) {
+                acc[e] = l == 0 ? cl * Lt[e] : acc[e] + cl * Lt[e];
+                if (l == 0) qsum[e] = 0;
             }
-            if (FINAL) Storage<S>::load4(a.fn, nb.c + ch.k0, base);
+            if (l == 0) {
+                // the implicit stages transport f^n first
 #pragma unroll
-            for (int e = 0; e < 4; ++e) fs[e] = base[e] - dt * acc[e];
-#pragma unroll
-            for (int q = 0; q < NQ; ++q) {
-                T fj[4];
-                Storage<S>::load4(a.fq[q], nb.c + ch.k0, fj);
+                for (int e = 0; e < 4; ++e) base[e] = FINAL ? cur.b[e] : cur.c[e];
+            }
+            // implicit term of the stage whose state this unit transports
+            constexpr int Q0 = NL - NQ;
+            if (l >= Q0) {
+                const int q = l - Q0 < NQ ? l - Q0 : 0;
                 GaussRow<T> gr;
                 gr.set(gq[q], ch.vy);
                 const T cq = (T)a.cq[q] * dtte;
 #pragma unroll
-                for (int e = 0; e < 4; ++e) fs[e] += cq * (gr.hat(gq[q], ch.vx[e]) - fj[e]);
+                for (int e = 0; e < 4; ++e) qsum[e] += cq * (gr.hat(gq[q], ch.vx[e]) - cur.c[e]);
             }
-            macc.add(ch, fs);
+            if (l == NL - 1) {
+                T fs[4];
 #pragma unroll
-            for (int e = 0; e < 4; ++e) lds.v[wave][m][lane][e] = fs[e];
-            if (FINAL && gc.valid) Storage<S>::store4(a.fout, nb.c + ch.k0, fs);
+                for (int e = 0; e < 4; ++e) fs[e] = (base[e] - dt * acc[e]) + qsum[e];
+                macc.add(ch, fs);
+#pragma unroll
+                for (int e = 0; e < 4; ++e) lds.v[wave][m][lane][e] = fs[e];
+                if (FINAL && gc.valid) Storage<S>::store4(a.fout + nb.c, (uint32_t)ch.k0, fs);
+            }
         }
-        if ((m & 3) == 3) macc.fold();
-        // keep each chunk's stencil loads inside its iteration: bounded register
-        // use, latency hidden by the other wavefronts of the CU
+        if (l == NL - 1 && (m & 3) == 3) macc.fold();
+        // bounded register use: at most two units' loads live at a time
         __builtin_amdgcn_sched_barrier(0);
     }
 
@@ -556,7 +601,7 @@ __global__ __launch_bounds__(64 * waves_per_block<C>(), ESBGK_STAGE_MIN_WAVES) v
                     const T Ghat = lds.g[wave][m][lane][e] * ((T)1 + ((d3 * aa + plin) * aa + pconst));
                     fv[e] = (lds.v[wave][m][lane][e] + lamt * Ghat) * inv1;
                 }
-                if (gc.valid) Storage<S>::store4(a.fout, nb.c + ch.k0, fv);
+                if (gc.valid) Storage<S>::store4(a.fout + nb.c, (uint32_t)ch.k0, fv);
                 if (want_l1) {
                     const T ey = ch.vy - uyt, qy = mq * ey * ey;
 #pragma unroll
@@ -643,7 +688,7 @@ __global__ __launch_bounds__(64 * waves_per_block<C>()) void fill_maxwellian_ker
                 const T G = glds[wave][m][lane][e];
                 v[e] = G + G * ((d3 * aa + plin) * aa + pconst);
             }
-            Storage<S>::store4(a.f, (size_t)cell * g.nv2 + ch.k0, v);
+            Storage<S>::store4(a.f + (size_t)cell * g.nv2, (uint32_t)ch.k0, v);
         }
     }
     raise_err(a.err, errbits, gc.valid && s == 0);
@@ -665,7 +710,7 @@ __global__ __launch_bounds__(256) void moments_kernel(MomArgs<S> a) {
         const Chunk<T> ch = chunk_of<T, L, NV>(s, m, g);
 #pragma unroll
         for (int e = 0; e < 4; ++e) fv[m][e] = 0;
-        if (ch.active) Storage<S>::load4(a.f, (size_t)cell * g.nv2 + ch.k0, fv[m]);
+        if (ch.active) Storage<S>::load4(a.f + (size_t)cell * g.nv2, (uint32_t)ch.k0, fv[m]);
     }
     double mo[7];
     group_moments<T, L, C, NV>(fv, s, g, mo);
@@ -749,8 +794,11 @@ static hipError_t stage_dispatch(const StageArgs<S> &a, int nmax, hipStream_t st
 #define ESBGK_CASE(NN, LL, CC)                                                                                     \
     if ((NN == 0) ? (sh.L == LL && sh.C == CC) : (a.g.nv == NN)) {                                                    \
         constexpr int WPB = waves_per_block<CC>();                                                                  \
-        hipLaunchKernelGGL((stage_kernel<S, NN, LL, CC, NL, NQ, FINAL>), dim3(grid_for(nmax, WPB * (64 / LL))),     \
-                           dim3(64 * WPB), 0, st, a);                                                               \
+        const dim3 grid(grid_for(nmax, WPB * (64 / LL))), block(64 * WPB);                                          \
+        if (a.g.recon == 0)                                                                                         \
+            hipLaunchKernelGGL((stage_kernel<S, NN, LL, CC, NL, NQ, FINAL, 0>), grid, block, 0, st, a);             \
+        else                                                                                                        \
+            hipLaunchKernelGGL((stage_kernel<S, NN, LL, CC, NL, NQ, FINAL, 1>), grid, block, 0, st, a);             \
         return hipGetLastError();                                                                                   \
     }
     ESBGK_STATIC_NV(ESBGK_CASE)
@@ -761,6 +809,9 @@ static hipError_t stage_dispatch(const StageArgs<S> &a, int nmax, hipStream_t st
 
 template <class S>
 hipError_t launch_stage(const StageArgs<S> &a, int nmax, hipStream_t st) {
+    // the kernels take the implicit terms' states from the last NQ transported arrays
+    for (int q = 0; q < a.nq; ++q)
+        if (a.nl - a.nq + q < 0 || a.fq[q] != a.fl[a.nl - a.nq + q]) return hipErrorInvalidValue;
     if (a.aii > 0.0) {
         if (a.nl < 1 || a.fl[0] != a.fn) return hipErrorInvalidValue;  // implicit stages transport f^n first
         if (a.nl == 1 && a.nq == 0) return stage_dispatch<S, 1, 0, false>(a, nmax, st);
