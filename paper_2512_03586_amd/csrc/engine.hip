@@ -74,7 +74,6 @@ int validate(const esbgk_config *c) {
     if (c->scheme != ESBGK_ARS222 && c->scheme != ESBGK_ARS233) return fail(ESBGK_EINVAL, "bad scheme");
     if (c->recon != ESBGK_UPWIND1 && c->recon != ESBGK_MINMOD2) return fail(ESBGK_EINVAL, "bad recon");
     if (c->precision < ESBGK_FP64 || c->precision > ESBGK_BF16) return fail(ESBGK_EINVAL, "bad precision");
-    if (c->precision == ESBGK_FP64 && c->nv > 32) return fail(ESBGK_EINVAL, "the FP64 path supports nv <= 32");
     if (c->indicator != ESBGK_IND_PLAIN && c->indicator != ESBGK_IND_FROZEN)
         return fail(ESBGK_EINVAL, "indicator mode not available");
     if (c->coupling != ESBGK_COUPLE_STAGE && c->coupling != ESBGK_COUPLE_STEP) return fail(ESBGK_EINVAL, "bad coupling");

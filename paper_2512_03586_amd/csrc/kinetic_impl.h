@@ -345,11 +345,14 @@ template <class T> struct MomentAcc {
 // Per-lane staging of the explicit stage values f* in LDS between the
 // explicit pass and the relaxation: each lane writes and reads back only its
 // own 16-byte (FP32) slots, so no barrier is needed.
-// Waves per block: 4, or 1 when a wave's LDS staging is large (C > 9).
-template <int C> __host__ __device__ constexpr int waves_per_block() { return C > 9 ? 1 : 4; }
+// Waves per block: 4, or 1 when four waves' LDS staging (f* and the sampled
+// Gaussian, 2 C 64 4 values of type T per wave) would exceed 80 KB.
+template <class T, int C> __host__ __device__ constexpr int waves_per_block() {
+    return 4 * (2 * C * 64 * 4 * (int)sizeof(T)) <= 80 * 1024 ? 4 : 1;
+}
 
 template <class T, int C> struct StageLds {
-    static constexpr int W = waves_per_block<C>();
+    static constexpr int W = waves_per_block<T, C>();
     T v[W][C][64][4];  // [wave in block][chunk][lane][node]: f*
     T g[W][C][64][4];  // sampled Gaussian of the relaxed state
 };
@@ -459,11 +462,12 @@ __device__ inline void gaussian_pass(T (&glds)[C][64][4], T (*vlds)[64][4], int 
 template <class T> __device__ constexpr double correction_tol() { return sizeof(T) == 8 ? 1e-9 : 1e-6; }
 
 template <class S, int NV, int L, int C, int NL, int NQ, bool FINAL, int RECON>
-__global__ __launch_bounds__(64 * waves_per_block<C>(), ESBGK_STAGE_MIN_WAVES) void stage_kernel(StageArgs<S> a) {
+__global__ __launch_bounds__((64 * waves_per_block<typename Storage<S>::T, C>()), ESBGK_STAGE_MIN_WAVES) void stage_kernel(
+    StageArgs<S> a) {
     using T = typename Storage<S>::T;
     __shared__ StageLds<T, C> lds;
     const Geom &g = a.g;
-    const GroupCell gc = group_cell<L, waves_per_block<C>()>(a.list, *a.count);
+    const GroupCell gc = group_cell<L, waves_per_block<T, C>()>(a.list, *a.count);
     if (gc.cell < 0) return;
     const int cell = gc.cell;
     const int lane = (int)(threadIdx.x & 63), wave = (int)(threadIdx.x >> 6);
@@ -650,11 +654,12 @@ __global__ __launch_bounds__(64 * waves_per_block<C>(), ESBGK_STAGE_MIN_WAVES) v
 // f = Mhat(U) at the listed cells (eq. Coupling_FluKin): the corrected sampled
 // Maxwellian, i.e. the corrected Gaussian with Tt = T I.
 template <class S, int NV, int L, int C>
-__global__ __launch_bounds__(64 * waves_per_block<C>()) void fill_maxwellian_kernel(FillArgs<S> a) {
+__global__ __launch_bounds__((64 * waves_per_block<typename Storage<S>::T, C>())) void fill_maxwellian_kernel(
+    FillArgs<S> a) {
     using T = typename Storage<S>::T;
-    __shared__ T glds[waves_per_block<C>()][C][64][4];
+    __shared__ T glds[waves_per_block<T, C>()][C][64][4];
     const Geom &g = a.g;
-    const GroupCell gc = group_cell<L, waves_per_block<C>()>(a.list, *a.count);
+    const GroupCell gc = group_cell<L, waves_per_block<T, C>()>(a.list, *a.count);
     if (gc.cell < 0) return;
     const int cell = gc.cell;
     const int lane = (int)(threadIdx.x & 63), wave = (int)(threadIdx.x >> 6);
@@ -793,7 +798,7 @@ static hipError_t stage_dispatch(const StageArgs<S> &a, int nmax, hipStream_t st
     const Shape sh = shape_for(a.g.nv2);
 #define ESBGK_CASE(NN, LL, CC)                                                                                     \
     if ((NN == 0) ? (sh.L == LL && sh.C == CC) : (a.g.nv == NN)) {                                                    \
-        constexpr int WPB = waves_per_block<CC>();                                                                  \
+        constexpr int WPB = waves_per_block<typename Storage<S>::T, CC>();                                                                  \
         const dim3 grid(grid_for(nmax, WPB * (64 / LL))), block(64 * WPB);                                          \
         if (a.g.recon == 0)                                                                                         \
             hipLaunchKernelGGL((stage_kernel<S, NN, LL, CC, NL, NQ, FINAL, 0>), grid, block, 0, st, a);             \
@@ -827,7 +832,7 @@ hipError_t launch_fill(const FillArgs<S> &a, int nmax, hipStream_t st) {
     const Shape sh = shape_for(a.g.nv2);
 #define ESBGK_CASE(NN, LL, CC)                                                                               \
     if ((NN == 0) ? (sh.L == LL && sh.C == CC) : (a.g.nv == NN)) {                                              \
-        constexpr int WPB = waves_per_block<CC>();                                                            \
+        constexpr int WPB = waves_per_block<typename Storage<S>::T, CC>();                                                            \
         hipLaunchKernelGGL((fill_maxwellian_kernel<S, NN, LL, CC>), dim3(grid_for(nmax, WPB * (64 / LL))),    \
                            dim3(64 * WPB), 0, st, a);                                                         \
         return hipGetLastError();                                                                             \

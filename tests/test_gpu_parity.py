@@ -153,6 +153,9 @@ FP64_CASES = [
     (dict(nx=17, ny=8, nv=8, vmax=6.0, seed=4), 0, 1),
     # resolved velocity grid (dv = 0.5): the correction takes its closed-form path
     (dict(nx=10, ny=9, nv=32, vmax=8.0, seed=5), 1, 1),
+    # compile-time 48^2 and 64^2 velocity grids (one wavefront per block in FP64)
+    (dict(nx=6, ny=5, nv=48, vmax=8.0, seed=6), 1, 1),
+    (dict(nx=5, ny=4, nv=64, vmax=10.0, seed=8), 1, 1),
 ]
 
 
