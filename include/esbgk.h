@@ -195,6 +195,94 @@ int esbgk_indicator(const esbgk_config *cfg, const double *d_prim, const double 
                     const double *d_l1, const uint8_t *d_mask_old, uint8_t *d_mask_new,
                     double *d_lambda, void *stream);
 
+/* ====================================================================
+ * Learned regime indicator (an addition to the paper's method; it has no
+ * counterpart there).  A network predicts, from the macroscopic state at the
+ * start of a step, which cells the plain criterion of Sec. 3.1.2 marks
+ * kinetic at any of the next K = learned_k steps.  With indicator = LEARNED
+ * the engine runs the plain criterion P only every K steps (the fallback and
+ * the judge of the prediction) and keeps the mask P | prediction for the next
+ * K steps, so that the regime update, the compaction and the fluid -> kinetic
+ * fills run once per K steps.
+ *
+ * Features of a cell (192 BF16 values): over its periodic 5 x 5 stencil
+ * (k = 5 (dj + 2) + (di + 2)), for stencil cell s and centre c,
+ *   x[7k+0] = rho_s/rho_c - 1, x[7k+1] = ux_s - ux_c, x[7k+2] = uy_s - uy_c,
+ *   x[7k+3] = T_s/T_c - 1, x[7k+4] = eps_s/(eps_s + 0.01),
+ *   x[7k+5] = A_s/(A_s + 1e-4) with A = eps^2 |grad u|^2,
+ *   x[7k+6] = B_s/(B_s + 1e-4) with B = eps^2 |grad T|^2 / T,
+ *   x[175] = the mask in use at c, x[176..191] = 0
+ * (central differences; FP64 + - * / in a fixed order, rounded FP32 -> BF16).
+ * Network: z = w3 . relu(W2^T relu(W1^T x + b1) + b2) + b3, 64 and 64 hidden
+ * units, weights used in BF16, biases in FP32, hidden activations stored in
+ * BF16, FP32 accumulation on the matrix cores.  Parameters travel as one flat
+ * FP32 vector of esbgk_mlp_param_count() values: W1 [192][64] (row = input),
+ * b1 [64], W2 [64][64], b2 [64], w3 [64], b3.  Training minimizes the mean
+ * weighted logistic loss w_pos y softplus(-z) + (1 - y) softplus(z) with
+ * bias-corrected Adam (beta1 0.9, beta2 0.999, eps 1e-8).
+ * ==================================================================== */
+
+typedef struct esbgk_mlp esbgk_mlp;
+
+/* Number of parameters (16577). */
+int esbgk_mlp_param_count(void);
+
+/* Device bytes for a network that trains on batches of up to max_batch
+ * samples (parameters, Adam moments, BF16 copies, gradient partials). */
+int esbgk_mlp_workspace_size(int max_batch, size_t *bytes);
+
+/* Create a network in the caller's device workspace (256-byte aligned, kept
+ * alive until esbgk_mlp_destroy()).  Weights are undefined until
+ * esbgk_mlp_set_weights(). */
+int esbgk_mlp_create(int max_batch, void *d_workspace, size_t bytes, esbgk_mlp **out);
+void esbgk_mlp_destroy(esbgk_mlp *net);
+const char *esbgk_mlp_last_error(void);
+
+/* Load / read the flat FP32 parameter vector (device pointers).  Loading
+ * resets the Adam state. */
+int esbgk_mlp_set_weights(esbgk_mlp *net, const float *d_params, void *stream);
+int esbgk_mlp_get_weights(esbgk_mlp *net, float *d_params, void *stream);
+
+/* Per-cell derived fields of nsnap snapshots on an nx x ny periodic grid of
+ * size lx x ly.  d_fields: device FP64 [nsnap][6][nx*ny] = (rho, ux, uy, T,
+ * eps, mask in use as 0.0 / 1.0); d_derived: device FP64 [nsnap][3][nx*ny]
+ * (eps/(eps+0.01), A/(A+1e-4), B/(B+1e-4)). */
+int esbgk_mlp_derived(int nx, int ny, double lx, double ly, const double *d_fields, int nsnap,
+                      double *d_derived, void *stream);
+
+/* Feature rows of n samples of nsnap snapshots: d_samples device int32
+ * [n][2] = (snapshot, cell); d_X device [n][192] BF16 bit patterns.  A
+ * sample outside [0, nsnap) x [0, nx*ny) gets a row of zeros. */
+int esbgk_mlp_features(int nx, int ny, const double *d_fields, const double *d_derived, int nsnap,
+                       const int32_t *d_samples, int n, uint16_t *d_X, void *stream);
+
+/* Logits of n feature rows (device FP32 [n]); any n >= 0. */
+int esbgk_mlp_forward(esbgk_mlp *net, const uint16_t *d_X, int n, float *d_logits, void *stream);
+
+/* Gradient of the mean weighted logistic loss over n <= max_batch samples
+ * (labels d_y device FP32 [n], 0 or 1) with respect to the parameters,
+ * written to d_grad (device FP32, flat order); d_loss (device FP32, may be
+ * NULL) receives the loss.  Deterministic (fixed reduction order). */
+int esbgk_mlp_gradients(esbgk_mlp *net, const uint16_t *d_X, const float *d_y, int n, float w_pos,
+                        float *d_grad, float *d_loss, void *stream);
+
+/* One Adam step on the same gradient (learning rate lr > 0). */
+int esbgk_mlp_train_step(esbgk_mlp *net, const uint16_t *d_X, const float *d_y, int n, float w_pos,
+                         float lr, float *d_loss, void *stream);
+
+/* Attach the predictor to a context configured with indicator = LEARNED:
+ * mask = P | (logit > threshold) at every check step.  With net = NULL the
+ * mask is P dilated by `dilation` cells along x and y (Chebyshev distance),
+ * the plain-every-K baseline.  The network must outlive its use. */
+int esbgk_set_learned(esbgk_ctx *ctx, esbgk_mlp *net, float threshold, int dilation);
+
+/* Judge counters of the learned indicator since esbgk_set_state(), summed
+ * over the check steps after the first: h_out[0] checks, h_out[1] cells
+ * with P = 1 outside the mask that was in use (missed), h_out[2] cells in
+ * the mask in use with P = 0 (extra), h_out[3] cells with P = 1.
+ * Synchronizes on the stream. */
+int esbgk_get_learned_stats(esbgk_ctx *ctx, int64_t *h_out, void *stream);
+
 #ifdef __cplusplus
 }
 #endif

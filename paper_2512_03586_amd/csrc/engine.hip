@@ -74,8 +74,9 @@ int validate(const esbgk_config *c) {
     if (c->scheme != ESBGK_ARS222 && c->scheme != ESBGK_ARS233) return fail(ESBGK_EINVAL, "bad scheme");
     if (c->recon != ESBGK_UPWIND1 && c->recon != ESBGK_MINMOD2) return fail(ESBGK_EINVAL, "bad recon");
     if (c->precision < ESBGK_FP64 || c->precision > ESBGK_BF16) return fail(ESBGK_EINVAL, "bad precision");
-    if (c->indicator != ESBGK_IND_PLAIN && c->indicator != ESBGK_IND_FROZEN)
-        return fail(ESBGK_EINVAL, "indicator mode not available");
+    if (c->indicator != ESBGK_IND_PLAIN && c->indicator != ESBGK_IND_FROZEN && c->indicator != ESBGK_IND_LEARNED)
+        return fail(ESBGK_EINVAL, "bad indicator mode");
+    if (c->indicator == ESBGK_IND_LEARNED && c->learned_k < 1) return fail(ESBGK_EINVAL, "learned_k must be >= 1");
     if (c->coupling != ESBGK_COUPLE_STAGE && c->coupling != ESBGK_COUPLE_STEP) return fail(ESBGK_EINVAL, "bad coupling");
     if (!(c->lx > 0) || !(c->ly > 0) || !(c->vmax > 0)) return fail(ESBGK_EINVAL, "lx, ly, vmax must be > 0");
     if (!(c->tau > 0)) return fail(ESBGK_EINVAL, "tau must be > 0");
@@ -87,7 +88,10 @@ int validate(const esbgk_config *c) {
 
 struct Layout {
     size_t f[3], U[4], gp[2], eps, l1, prim, mask, mask_old, cls, kin, buf, newk, blockcounts, counts, err,
-        bad, kin_total, total;
+        bad, kin_total;
+    // learned indicator (indicator == LEARNED only)
+    size_t fields, derived, X, samples, logits, pmask, lcount;
+    size_t total;
 };
 
 Layout layout(const esbgk_config *c) {
@@ -112,6 +116,14 @@ Layout layout(const esbgk_config *c) {
     L.err = take(sizeof(int));
     L.bad = take(sizeof(int));
     L.kin_total = take(sizeof(long long));
+    const bool learned = c->indicator == ESBGK_IND_LEARNED;
+    L.fields = take(learned ? 6 * nc * sizeof(double) : 0);
+    L.derived = take(learned ? 3 * nc * sizeof(double) : 0);
+    L.X = take(learned ? nc * 192 * sizeof(uint16_t) : 0);
+    L.samples = take(learned ? 2 * nc * sizeof(int) : 0);
+    L.logits = take(learned ? nc * sizeof(float) : 0);
+    L.pmask = take(learned ? nc : 0);
+    L.lcount = take(learned ? 4 * sizeof(long long) : 0);
     L.total = off;
     return L;
 }
@@ -137,6 +149,16 @@ struct esbgk_ctx {
     int *kin = nullptr, *buf = nullptr, *newk = nullptr, *blockcounts = nullptr, *counts = nullptr,
         *err = nullptr, *bad = nullptr;
     long long *kin_total = nullptr;
+    // learned indicator
+    esbgk_mlp *net = nullptr;
+    float threshold = 0.0f;
+    int dilation = 0;
+    double *lfields = nullptr, *lderived = nullptr;
+    uint16_t *lX = nullptr;
+    int *lsamples = nullptr;
+    float *llogits = nullptr;
+    uint8_t *pmask = nullptr;
+    long long *lcount = nullptr;
     int64_t steps = 0;
     double time = 0.0;
     bool have_state = false;
@@ -270,6 +292,34 @@ int euler_stage(esbgk_ctx *c, int i, hipStream_t st, double *Uout) {
     return ESBGK_OK;
 }
 
+// Regime update of a check step of the learned indicator: the plain criterion
+// P (the fallback and the judge), and the mask for the next learned_k steps,
+// P | (network logit > threshold), or, without a network, P dilated by
+// `dilation` cells (the plain-every-K baseline).  Counts the cells where P
+// disagrees with the mask that was in use (missed: P and not in use; extra:
+// in use and not P).
+int learned_update(esbgk_ctx *c, hipStream_t st) {
+    if (!c->net && c->dilation < 0) return fail(ESBGK_EINVAL, "learned indicator without a network or dilation");
+    HIPCHK(launch_prim(c->U[0], c->prim, c->nc, st));
+    std::swap(c->mask_old, c->mask);
+    IndicatorArgs ia = indicator_args(&c->cfg);
+    ia.prim = c->prim; ia.eps = c->eps; ia.l1 = c->l1; ia.mask_old = c->mask_old; ia.mask_new = c->pmask;
+    HIPCHK(launch_indicator(ia, st));
+    const float *logits = nullptr;
+    if (c->net) {
+        HIPCHK(launch_learned_fields(c->prim, c->eps, c->mask_old, c->lfields, c->nc, st));
+        int rc;
+        if ((rc = esbgk_mlp_derived(c->cfg.nx, c->cfg.ny, c->cfg.lx, c->cfg.ly, c->lfields, 1, c->lderived, st)) ||
+            (rc = esbgk_mlp_features(c->cfg.nx, c->cfg.ny, c->lfields, c->lderived, 1, c->lsamples, c->nc, c->lX, st)) ||
+            (rc = esbgk_mlp_forward(c->net, c->lX, c->nc, c->llogits, st)))
+            return fail(rc, "learned indicator: %s", esbgk_mlp_last_error());
+        logits = c->llogits;
+    }
+    HIPCHK(launch_learned_combine(c->pmask, logits, c->threshold, c->net ? 0 : c->dilation, c->mask_old, c->mask,
+                                  c->cls, c->cfg.nx, c->cfg.ny, c->steps > 0 ? c->lcount : nullptr, st));
+    return ESBGK_OK;
+}
+
 template <class S> int run_step(esbgk_ctx *c, hipStream_t st) {
     const size_t nc = (size_t)c->nc;
     const bool loc = c->cfg.coupling == ESBGK_COUPLE_STEP;
@@ -283,6 +333,10 @@ template <class S> int run_step(esbgk_ctx *c, hipStream_t st) {
         HIPCHK(launch_indicator(ia, st));
         if ((rc = regime_lists(c, c->mask_old, st))) return rc;
         // fluid -> kinetic: f = Mhat(U) (eq. Coupling_FluKin); kinetic -> fluid keeps U = moments(f)
+        if ((rc = fill_list<S>(c, c->f[0], c->U[0], c->newk, c->counts + 2, st))) return rc;
+    } else if (c->cfg.indicator == ESBGK_IND_LEARNED && c->steps % c->cfg.learned_k == 0) {
+        if ((rc = learned_update(c, st))) return rc;
+        if ((rc = regime_lists(c, c->mask_old, st))) return rc;
         if ((rc = fill_list<S>(c, c->f[0], c->U[0], c->newk, c->counts + 2, st))) return rc;
     }
     HIPCHK(launch_accumulate_count(c->counts, c->kin_total, st));
@@ -399,6 +453,15 @@ int esbgk_create(const esbgk_config *cfg, void *d_workspace, size_t bytes, esbgk
     c->err = (int *)(w + L.err);
     c->bad = (int *)(w + L.bad);
     c->kin_total = (long long *)(w + L.kin_total);
+    if (cfg->indicator == ESBGK_IND_LEARNED) {
+        c->lfields = (double *)(w + L.fields);
+        c->lderived = (double *)(w + L.derived);
+        c->lX = (uint16_t *)(w + L.X);
+        c->lsamples = (int *)(w + L.samples);
+        c->llogits = (float *)(w + L.logits);
+        c->pmask = (uint8_t *)(w + L.pmask);
+        c->lcount = (long long *)(w + L.lcount);
+    }
     *out = c;
     return ESBGK_OK;
 }
@@ -424,6 +487,10 @@ int esbgk_set_state(esbgk_ctx *c, const double *d_rho, const double *d_ux, const
     HIPCHK(hipMemsetAsync(c->mask_old, 0, c->nc, st));
     HIPCHK(hipMemsetAsync(c->l1, 0, c->nc * sizeof(double), st));
     HIPCHK(hipMemsetAsync(c->kin_total, 0, sizeof(long long), st));
+    if (c->lcount) {
+        HIPCHK(hipMemsetAsync(c->lcount, 0, 4 * sizeof(long long), st));
+        HIPCHK(launch_identity_samples(c->lsamples, c->nc, st));
+    }
     if ((rc = regime_lists(c, nullptr, st))) return rc;
     c->steps = 0;
     c->time = 0.0;
@@ -553,6 +620,29 @@ int esbgk_get_stats(esbgk_ctx *c, esbgk_stats *out, void *stream) {
     out->error_flags = err;
     out->kinetic_cell_steps = total;
     if (err) return fail(ESBGK_ENONPHYS, "non-physical state met during a step (flags 0x%x)", err);
+    return ESBGK_OK;
+}
+
+int esbgk_set_learned(esbgk_ctx *c, esbgk_mlp *net, float threshold, int dilation) {
+    if (!c) return fail(ESBGK_EINVAL, "null context");
+    if (c->cfg.indicator != ESBGK_IND_LEARNED) return fail(ESBGK_EINVAL, "context not configured for the learned indicator");
+    if (!net && dilation < 0) return fail(ESBGK_EINVAL, "need a network or a dilation radius >= 0");
+    if (dilation > 64) return fail(ESBGK_EINVAL, "dilation radius > 64");
+    if (!(threshold == threshold)) return fail(ESBGK_EINVAL, "threshold is NaN");
+    c->net = net;
+    c->threshold = threshold;
+    c->dilation = net ? 0 : dilation;
+    return ESBGK_OK;
+}
+
+int esbgk_get_learned_stats(esbgk_ctx *c, int64_t *h_out, void *stream) {
+    if (!c) return fail(ESBGK_EINVAL, "null context");
+    if (!h_out) return fail(ESBGK_EINVAL, "null output");
+    if (!c->lcount) return fail(ESBGK_EINVAL, "context not configured for the learned indicator");
+    long long v[4];
+    HIPCHK(hipMemcpyAsync(v, c->lcount, sizeof v, hipMemcpyDeviceToHost, (hipStream_t)stream));
+    HIPCHK(hipStreamSynchronize((hipStream_t)stream));
+    for (int q = 0; q < 4; ++q) h_out[q] = v[q];
     return ESBGK_OK;
 }
 

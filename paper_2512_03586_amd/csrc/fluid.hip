@@ -376,6 +376,70 @@ __global__ void accumulate_count_kernel(const int *counts, long long *total) {
 
 static inline unsigned cells_grid(int n) { return (unsigned)((n + 255) / 256 > 0 ? (n + 255) / 256 : 1); }
 
+// ------------------------------------------------- learned indicator glue
+
+// Feature fields of the current state: [6][nc] = (rho, ux, uy, T, eps, mask in use).
+__global__ void learned_fields_kernel(const double *prim, const double *eps, const uint8_t *mask, double *fields,
+                                      int nc) {
+    const int c = blockIdx.x * blockDim.x + threadIdx.x;
+    if (c >= nc) return;
+    const size_t n = (size_t)nc;
+#pragma unroll
+    for (int q = 0; q < 4; ++q) fields[q * n + c] = prim[q * n + c];
+    fields[4 * n + c] = eps[c];
+    fields[5 * n + c] = mask[c] ? 1.0 : 0.0;
+}
+
+__device__ inline void count_add(long long *counters, int q, bool pred) {
+    const int n = __syncthreads_count(pred);
+    if (threadIdx.x == 0 && n) atomicAdd((unsigned long long *)&counters[q], (unsigned long long)n);
+}
+
+// Mask of a check step: plain | (logit > threshold), or the plain mask
+// dilated by r cells (r > 0: this pass takes the maximum along x into tmp).
+__global__ void learned_combine_kernel(const uint8_t *plain, const float *logits, float threshold, int r,
+                                       const uint8_t *in_use, uint8_t *out, uint8_t *tmp, int nx, int ny,
+                                       long long *counters) {
+    const int c = blockIdx.x * blockDim.x + threadIdx.x;
+    const int nc = nx * ny;
+    const bool live = c < nc;
+    const bool p = live && plain[c];
+    if (live) {
+        if (r > 0) {
+            const int i = c % nx, j = c / nx;
+            uint8_t m = 0;
+            for (int d = -r; d <= r; ++d) m |= plain[(size_t)j * nx + wrapc(i + d, nx)];
+            tmp[c] = m;
+        } else {
+            out[c] = (uint8_t)(p || (logits && logits[c] > threshold));
+        }
+    }
+    if (counters) {
+        const bool u = live && in_use[c];
+        count_add(counters, 1, p && !u);
+        count_add(counters, 2, u && !p);
+        count_add(counters, 3, p);
+        if (c == 0) atomicAdd((unsigned long long *)&counters[0], 1ull);
+    }
+}
+
+// Second pass of the dilation: maximum along y.
+__global__ void dilate_y_kernel(const uint8_t *tmp, uint8_t *out, int nx, int ny, int r) {
+    const int c = blockIdx.x * blockDim.x + threadIdx.x;
+    if (c >= nx * ny) return;
+    const int i = c % nx, j = c / nx;
+    uint8_t m = 0;
+    for (int d = -r; d <= r; ++d) m |= tmp[(size_t)wrapc(j + d, ny) * nx + i];
+    out[c] = m;
+}
+
+__global__ void identity_samples_kernel(int *samples, int nc) {
+    const int c = blockIdx.x * blockDim.x + threadIdx.x;
+    if (c >= nc) return;
+    samples[2 * c] = 0;
+    samples[2 * c + 1] = c;
+}
+
 hipError_t launch_euler(const EulerArgs &a, hipStream_t st) {
     const dim3 grid((unsigned)((a.nx + ET - 1) / ET), (unsigned)((a.ny + ET - 1) / ET));
     hipLaunchKernelGGL(euler_stage_kernel, grid, dim3(ET * ET), 0, st, a);
@@ -433,6 +497,28 @@ hipError_t launch_accumulate_count(const int *counts, long long *total, hipStrea
 
 hipError_t launch_zero_fluid_l1(const uint8_t *mask, double *l1, int nc, hipStream_t st) {
     hipLaunchKernelGGL(zero_fluid_l1_kernel, dim3(cells_grid(nc)), dim3(256), 0, st, mask, l1, nc);
+    return hipGetLastError();
+}
+
+hipError_t launch_learned_fields(const double *prim, const double *eps, const uint8_t *mask, double *fields, int nc,
+                                 hipStream_t st) {
+    hipLaunchKernelGGL(learned_fields_kernel, dim3(cells_grid(nc)), dim3(256), 0, st, prim, eps, mask, fields, nc);
+    return hipGetLastError();
+}
+
+hipError_t launch_learned_combine(const uint8_t *plain, const float *logits, float threshold, int dilation,
+                                  const uint8_t *in_use, uint8_t *out, uint8_t *tmp, int nx, int ny,
+                                  long long *counters, hipStream_t st) {
+    const int nc = nx * ny;
+    hipLaunchKernelGGL(learned_combine_kernel, dim3(cells_grid(nc)), dim3(256), 0, st, plain, logits, threshold,
+                       dilation, in_use, out, tmp, nx, ny, counters);
+    if (dilation > 0)
+        hipLaunchKernelGGL(dilate_y_kernel, dim3(cells_grid(nc)), dim3(256), 0, st, tmp, out, nx, ny, dilation);
+    return hipGetLastError();
+}
+
+hipError_t launch_identity_samples(int *samples, int nc, hipStream_t st) {
+    hipLaunchKernelGGL(identity_samples_kernel, dim3(cells_grid(nc)), dim3(256), 0, st, samples, nc);
     return hipGetLastError();
 }
 

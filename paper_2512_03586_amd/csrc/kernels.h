@@ -90,6 +90,12 @@ hipError_t launch_get_prim(const double *U, double *rho, double *ux, double *uy,
                            hipStream_t st);
 hipError_t launch_accumulate_count(const int *counts, long long *total, hipStream_t st);
 hipError_t launch_zero_fluid_l1(const uint8_t *mask, double *l1, int nc, hipStream_t st);
+hipError_t launch_learned_fields(const double *prim, const double *eps, const uint8_t *mask, double *fields, int nc,
+                                 hipStream_t st);
+hipError_t launch_learned_combine(const uint8_t *plain, const float *logits, float threshold, int dilation,
+                                  const uint8_t *in_use, uint8_t *out, uint8_t *tmp, int nx, int ny,
+                                  long long *counters, hipStream_t st);
+hipError_t launch_identity_samples(int *samples, int nc, hipStream_t st);
 int scan_positions(int nx, int ny);
 int scan_nblocks(int nx, int ny);
 

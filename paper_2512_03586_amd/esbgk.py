@@ -84,6 +84,18 @@ def lib() -> C.CDLL:
             "esbgk_indicator": [P, _VP, _VP, _VP, _VP, _VP, _VP, _VP],
             "esbgk_set_timing": [_VP, C.c_int],
             "esbgk_kernel_times": [_VP, C.POINTER(C.c_double), C.POINTER(C.c_int64), C.c_int],
+            "esbgk_mlp_param_count": [],
+            "esbgk_mlp_workspace_size": [C.c_int, C.POINTER(C.c_size_t)],
+            "esbgk_mlp_create": [C.c_int, _VP, C.c_size_t, C.POINTER(_VP)],
+            "esbgk_mlp_set_weights": [_VP, _VP, _VP],
+            "esbgk_mlp_get_weights": [_VP, _VP, _VP],
+            "esbgk_mlp_derived": [C.c_int, C.c_int, C.c_double, C.c_double, _VP, C.c_int, _VP, _VP],
+            "esbgk_mlp_features": [C.c_int, C.c_int, _VP, _VP, C.c_int, _VP, C.c_int, _VP, _VP],
+            "esbgk_mlp_forward": [_VP, _VP, C.c_int, _VP, _VP],
+            "esbgk_mlp_gradients": [_VP, _VP, _VP, C.c_int, C.c_float, _VP, _VP, _VP],
+            "esbgk_mlp_train_step": [_VP, _VP, _VP, C.c_int, C.c_float, C.c_float, _VP, _VP],
+            "esbgk_set_learned": [_VP, _VP, C.c_float, C.c_int],
+            "esbgk_get_learned_stats": [_VP, C.POINTER(C.c_int64), _VP],
         }
         for name, args in sig.items():
             fn = getattr(L, name)
@@ -93,6 +105,10 @@ def lib() -> C.CDLL:
         L.esbgk_destroy.restype = None
         L.esbgk_last_error.argtypes = []
         L.esbgk_last_error.restype = C.c_char_p
+        L.esbgk_mlp_destroy.argtypes = [_VP]
+        L.esbgk_mlp_destroy.restype = None
+        L.esbgk_mlp_last_error.argtypes = []
+        L.esbgk_mlp_last_error.restype = C.c_char_p
         _lib = L
     return _lib
 
@@ -204,7 +220,134 @@ def esbgk_kernel_times(ctx, reset: bool = True):
     return list(ms), list(n)
 
 
+def _mcheck(rc: int) -> int:
+    if rc != OK:
+        raise EsbgkError(rc, lib().esbgk_mlp_last_error().decode())
+    return rc
+
+
+def esbgk_mlp_param_count() -> int:
+    return lib().esbgk_mlp_param_count()
+
+
+def esbgk_mlp_workspace_size(max_batch: int) -> int:
+    n = C.c_size_t(0)
+    _mcheck(lib().esbgk_mlp_workspace_size(int(max_batch), C.byref(n)))
+    return n.value
+
+
+def esbgk_mlp_create(max_batch: int, workspace: torch.Tensor) -> C.c_void_p:
+    net = C.c_void_p()
+    _mcheck(lib().esbgk_mlp_create(int(max_batch), _ptr(workspace), workspace.numel(), C.byref(net)))
+    return net
+
+
+def esbgk_mlp_destroy(net):
+    lib().esbgk_mlp_destroy(net)
+
+
+def esbgk_mlp_set_weights(net, params, stream=None):
+    return _mcheck(lib().esbgk_mlp_set_weights(net, _ptr(params), _stream(stream)))
+
+
+def esbgk_mlp_get_weights(net, params, stream=None):
+    return _mcheck(lib().esbgk_mlp_get_weights(net, _ptr(params), _stream(stream)))
+
+
+def esbgk_mlp_derived(nx, ny, lx, ly, fields, nsnap, derived, stream=None):
+    return _mcheck(lib().esbgk_mlp_derived(int(nx), int(ny), float(lx), float(ly), _ptr(fields), int(nsnap),
+                                           _ptr(derived), _stream(stream)))
+
+
+def esbgk_mlp_features(nx, ny, fields, derived, nsnap, samples, n, X, stream=None):
+    return _mcheck(lib().esbgk_mlp_features(int(nx), int(ny), _ptr(fields), _ptr(derived), int(nsnap), _ptr(samples),
+                                            int(n), _ptr(X), _stream(stream)))
+
+
+def esbgk_mlp_forward(net, X, n, logits, stream=None):
+    return _mcheck(lib().esbgk_mlp_forward(net, _ptr(X), int(n), _ptr(logits), _stream(stream)))
+
+
+def esbgk_mlp_gradients(net, X, y, n, w_pos, grad, loss=None, stream=None):
+    return _mcheck(lib().esbgk_mlp_gradients(net, _ptr(X), _ptr(y), int(n), float(w_pos), _ptr(grad), _ptr(loss),
+                                             _stream(stream)))
+
+
+def esbgk_mlp_train_step(net, X, y, n, w_pos, lr, loss=None, stream=None):
+    return _mcheck(lib().esbgk_mlp_train_step(net, _ptr(X), _ptr(y), int(n), float(w_pos), float(lr), _ptr(loss),
+                                              _stream(stream)))
+
+
+def esbgk_set_learned(ctx, net, threshold: float, dilation: int = 0):
+    return _check(lib().esbgk_set_learned(ctx, net, float(threshold), int(dilation)))
+
+
+def esbgk_get_learned_stats(ctx, stream=None):
+    """(checks, missed, extra, plain-kinetic cells) summed over check steps."""
+    out = (C.c_int64 * 4)()
+    _check(lib().esbgk_get_learned_stats(ctx, out, _stream(stream)))
+    return tuple(out)
+
+
 # ---------------------------------------------------------------- convenience
+
+class Network:
+    """The learned-indicator network plus its workspace."""
+
+    def __init__(self, max_batch: int, device: str = "cuda"):
+        if not torch.cuda.is_available():
+            raise RuntimeError("esbgk needs a GPU (no CPU path exists)")
+        self.max_batch = int(max_batch)
+        self.nparam = esbgk_mlp_param_count()
+        nbytes = esbgk_mlp_workspace_size(max_batch)
+        self.workspace = torch.empty(nbytes + 256, dtype=torch.uint8, device=device)
+        off = (-self.workspace.data_ptr()) % 256
+        self._ws = self.workspace[off:off + nbytes]
+        self.net = esbgk_mlp_create(max_batch, self._ws)
+        self.device = device
+        self.loss = torch.zeros(1, dtype=torch.float32, device=device)
+
+    def __del__(self):
+        try:
+            if getattr(self, "net", None) is not None:
+                esbgk_mlp_destroy(self.net)
+                self.net = None
+        except Exception:
+            pass
+
+    def set_weights(self, params):
+        esbgk_mlp_set_weights(self.net, torch.as_tensor(params, dtype=torch.float32).to(self.device).contiguous())
+
+    def get_weights(self):
+        out = torch.empty(self.nparam, dtype=torch.float32, device=self.device)
+        esbgk_mlp_get_weights(self.net, out)
+        return out
+
+    def forward(self, X):
+        z = torch.empty(X.shape[0], dtype=torch.float32, device=self.device)
+        esbgk_mlp_forward(self.net, X, X.shape[0], z)
+        return z
+
+    def gradients(self, X, y, w_pos):
+        g = torch.empty(self.nparam, dtype=torch.float32, device=self.device)
+        esbgk_mlp_gradients(self.net, X, y, X.shape[0], w_pos, g, self.loss)
+        return g, self.loss
+
+    def train_step(self, X, y, w_pos, lr):
+        esbgk_mlp_train_step(self.net, X, y, X.shape[0], w_pos, lr, self.loss)
+        return self.loss
+
+
+def mlp_features(nx, ny, lx, ly, fields, samples):
+    """BF16 feature rows (as int16 bit patterns, [n][192]) of samples (int32
+    [n][2] = snapshot, cell) of the snapshot fields (FP64 [nsnap][6][nc])."""
+    nsnap = fields.shape[0]
+    derived = torch.empty(nsnap, 3, nx * ny, dtype=torch.float64, device=fields.device)
+    esbgk_mlp_derived(nx, ny, lx, ly, fields, nsnap, derived)
+    X = torch.empty(samples.shape[0], 192, dtype=torch.int16, device=fields.device)
+    esbgk_mlp_features(nx, ny, fields, derived, nsnap, samples, samples.shape[0], X)
+    return X
+
 
 class Engine:
     """A context plus its workspace (a torch uint8 device tensor)."""
@@ -277,3 +420,10 @@ class Engine:
 
     def stats(self, check=True):
         return esbgk_get_stats(self.ctx, check=check)
+
+    def set_learned(self, network=None, threshold=0.0, dilation=0):
+        self._network = network   # keep it alive while attached
+        esbgk_set_learned(self.ctx, network.net if network is not None else None, threshold, dilation)
+
+    def learned_stats(self):
+        return esbgk_get_learned_stats(self.ctx)

@@ -1,0 +1,179 @@
+"""GPU tests of the learned regime indicator through the C ABI, against the
+FP64 oracle of oracle/mlp.py on the same inputs.
+
+Bars: features bit-exact (both sides evaluate the same correctly rounded FP64
+operations and round FP32 -> BF16); logits within 2e-3 of the largest logit
+(FP32 accumulation, and hidden activations that both sides round to BF16
+from slightly different sums); gradients within 1e-3 relative in norm per
+parameter tensor (the backward products carry the FP32 gradient matrices as
+BF16 hi + lo pairs, about 2^-17 relative each); one Adam step within 1e-5 of
+the oracle's on the parameters whose gradient is not tiny.
+"""
+import math
+
+import numpy as np
+import pytest
+import torch
+
+from oracle import mlp as M
+from paper_2512_03586_amd import inputs
+
+pytestmark = pytest.mark.gpu
+
+E = L = None
+
+
+@pytest.fixture(scope="module", autouse=True)
+def _engine_module():
+    global E, L
+    if not torch.cuda.is_available():
+        pytest.fail("no GPU visible")
+    from paper_2512_03586_amd import esbgk, learned
+    esbgk.lib()
+    E, L = esbgk, learned
+    yield
+
+
+def random_state(nx, ny, seed):
+    rng = np.random.default_rng(seed)
+    nc = nx * ny
+    return dict(rho=1 + 0.3 * rng.uniform(-1, 1, nc), ux=rng.uniform(-1, 1, nc), uy=rng.uniform(-1, 1, nc),
+                T=1 + 0.5 * rng.uniform(0, 1, nc), eps=10 ** rng.uniform(-4, 0, nc),
+                mask=(rng.uniform(size=nc) < 0.4).astype(np.uint8))
+
+
+def fields_of(s):
+    return torch.tensor(np.stack([s["rho"], s["ux"], s["uy"], s["T"], s["eps"], s["mask"].astype(np.float64)])[None],
+                        dtype=torch.float64, device="cuda").contiguous()
+
+
+def bits(X):
+    return torch.tensor(M.bf16_bits(X).view(np.int16), device="cuda").contiguous()
+
+
+@pytest.mark.parametrize("nx,ny", [(13, 9), (32, 32), (5, 4)])
+def test_features_bit_exact(nx, ny):
+    s = random_state(nx, ny, nx + ny)
+    Xo = M.features(nx, ny, 1.0, 0.7, s["rho"], s["ux"], s["uy"], s["T"], s["eps"], s["mask"])
+    cells = np.arange(nx * ny)[::-1].copy()
+    smp = torch.tensor(np.stack([np.zeros_like(cells), cells], 1), dtype=torch.int32, device="cuda").contiguous()
+    Xg = E.mlp_features(nx, ny, 1.0, 0.7, fields_of(s), smp).cpu().numpy().view(np.uint16)
+    np.testing.assert_array_equal(Xg, M.bf16_bits(Xo[cells]))
+
+
+def _net_and_batch(n, seed):
+    s = random_state(40, 30, seed)
+    cells = np.random.default_rng(seed).integers(0, 1200, n)
+    X = M.features(40, 30, 1.0, 1.0, s["rho"], s["ux"], s["uy"], s["T"], s["eps"], s["mask"], cells)
+    p = M.init_params(seed)
+    rng = np.random.default_rng(seed + 1)
+    for k in ("b1", "b2"):
+        p[k] = M.to_f32(rng.uniform(-0.2, 0.2, 64)).astype(np.float64)
+    p["b3"] = np.asarray(0.1)
+    y = (rng.uniform(size=n) < 0.35).astype(np.float64)
+    net = E.Network(max(n, 64))
+    net.set_weights(torch.tensor(M.flatten(p), dtype=torch.float32))
+    return net, p, X, y
+
+
+@pytest.mark.parametrize("n", [64, 1000, 4096 + 37])
+def test_mfma_forward_matches_oracle(n):
+    net, p, X, y = _net_and_batch(n, 3)
+    zg = net.forward(bits(X)).cpu().numpy().astype(np.float64)
+    zo, _ = M.forward(p, X)
+    assert np.abs(zg - zo).max() <= 2e-3 * np.abs(zo).max(), np.abs(zg - zo).max()
+
+
+@pytest.mark.parametrize("n", [64, 3000])
+def test_gradients_match_oracle(n):
+    net, p, X, y = _net_and_batch(n, 5)
+    g, loss = net.gradients(bits(X), torch.tensor(y, dtype=torch.float32, device="cuda"), 3.0)
+    lo, go = M.loss_and_grads(p, X, y, 3.0)
+    assert abs(loss.item() - lo) <= 1e-4 * abs(lo)
+    gg = M.unflatten(g.cpu().numpy().astype(np.float64))
+    for k in M.ORDER:
+        num = np.linalg.norm(np.ravel(gg[k] - go[k]))
+        den = np.linalg.norm(np.ravel(go[k]))
+        assert num <= 1e-3 * den, (k, num / den)
+
+
+def test_adam_step_matches_oracle():
+    n = 2048
+    net, p, X, y = _net_and_batch(n, 7)
+    lr = 1e-3
+    net.train_step(bits(X), torch.tensor(y, dtype=torch.float32, device="cuda"), 2.0, lr)
+    pg = net.get_weights().cpu().numpy().astype(np.float64)
+    _, go = M.loss_and_grads(p, X, y, 2.0)
+    gflat = M.flatten(go)
+    p1, _, _ = M.adam(M.flatten(p), gflat, np.zeros(M.NPARAM), np.zeros(M.NPARAM), 1, lr)
+    big = np.abs(gflat) > 1e-2 * np.abs(gflat).max()
+    assert big.sum() > 100
+    assert np.abs(pg[big] - p1[big]).max() <= 1e-5 * (1 + np.abs(p1[big]).max())
+    # padding inputs keep zero weights
+    W1 = pg[:192 * 64].reshape(192, 64)
+    assert np.all(W1[176:] == 0.0)
+
+
+def test_training_separates_a_learnable_rule():
+    """The labels are a fixed function of the features: the loss falls."""
+    s = random_state(64, 64, 11)
+    X = M.features(64, 64, 1.0, 1.0, s["rho"], s["ux"], s["uy"], s["T"], s["eps"], s["mask"])
+    y = ((X[:, 7 * 12 + 4] > 0.5) | (X[:, 7 * 12 + 5] > 0.3)).astype(np.float64)
+    Xb, yb = bits(X), torch.tensor(y, dtype=torch.float32, device="cuda")
+    net = E.Network(4096)
+    net.set_weights(L.initial_params(0))
+    first = None
+    for it in range(300):
+        idx = torch.randint(0, 4096, (4096,), device="cuda")
+        loss = net.train_step(Xb[idx].contiguous(), yb[idx].contiguous(), 1.0, 3e-3).item()
+        first = first if first is not None else loss
+    z = net.forward(Xb).cpu().numpy()
+    acc = ((z > 0) == (y > 0.5)).mean()
+    assert loss < 0.3 * first and acc > 0.97, (first, loss, acc)
+
+
+def test_learned_mode_counters_and_fallback():
+    """With a network that predicts nothing (large negative bias) the mask at a
+    check step is the plain mask; the judge counts its disagreements with the
+    mask in use."""
+    d = inputs.riemann4(nx=48, ny=48, nv=16, vmax=8.0, seed=2)
+    p = M.init_params(1)
+    p["b3"] = np.asarray(-1e4)
+    net = E.Network(64)
+    net.set_weights(torch.tensor(M.flatten(p), dtype=torch.float32))
+    K = 4
+    lr = L.run("learned", d, nx=48, nv=16, vmax=8.0, steps=3 * K + 1, K=K, net=net, threshold=0.0)
+    checks, missed, extra, plain = lr["judge"]
+    assert checks == 3 and plain > 0 and missed + extra >= 0
+    # the same run with a zero dilation radius and no network agrees
+    dr = L.run("dilated", d, nx=48, nv=16, vmax=8.0, steps=3 * K + 1, K=K, dilation=0)
+    np.testing.assert_array_equal(lr["mask"], dr["mask"])
+    np.testing.assert_allclose(lr["prim"], dr["prim"], rtol=1e-12, atol=1e-12)
+
+
+def test_trained_indicator_gains_over_dilated_plain_every_k():
+    """Trained on plain runs of the four-quadrant generator, the network keeps
+    fewer kinetic cell-steps than the plain-every-K baseline with dilation by
+    ceil(K CFL sqrt 2) cells, at a small missed-cell rate and a density error
+    against the plain-every-step run of the same size as the baseline's."""
+    kw = dict(nx=96, nv=16, vmax=10.0, steps=100, K=10)
+    train = L.collect(range(0, 6), **kw)
+    val = L.collect(range(100, 102), **kw)
+    net, res = L.train(train, val, iters=600, batch=8192, lr=3e-3, w_pos=4.0, miss=2e-3)
+    d = inputs.riemann4(nx=96, ny=96, nv=16, vmax=10.0, seed=1000)
+    common = dict(nx=96, nv=16, vmax=10.0, steps=100, K=10)
+    plain = L.run("plain", d, nx=96, nv=16, vmax=10.0, steps=100)
+    lrn = L.run("learned", d, net=net, threshold=res.threshold, **common)
+    dil = L.run("dilated", d, dilation=L.dilation_radius(10), **common)
+
+    def rho_err(r):
+        return float(np.abs(r["prim"][0] - plain["prim"][0]).sum() / np.abs(plain["prim"][0]).sum())
+
+    nc = 96 * 96
+    checks, missed, extra, _ = lrn["judge"]
+    miss_rate = missed / (checks * nc)
+    print("plain", plain["kinetic_cell_steps"], "learned", lrn["kinetic_cell_steps"], "dilated",
+          dil["kinetic_cell_steps"], "miss rate", miss_rate, "err", rho_err(lrn), rho_err(dil), res)
+    assert lrn["kinetic_cell_steps"] < 0.9 * dil["kinetic_cell_steps"]
+    assert miss_rate <= 5e-3
+    assert rho_err(lrn) <= max(2 * rho_err(dil), 1e-4)

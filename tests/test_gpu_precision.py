@@ -9,10 +9,13 @@ kinetic 64^2 x 48^2 copy makes the stored-precision error visible in every
 cell (in the coupled run only the two shear layers are kinetic).
 
 Reported per form: the relative L1 error of rho, u and T,
-||x - x_oracle||_1 / ||x_oracle||_1.  Bars: FP64 1e-10; FP32 2e-5; BF16 (f
-rounded to 8 significant bits at every stage write) 1e-4 on rho and 1e-3 on
-u and T in the coupled run, 2e-3 on every field in the fully kinetic run.
-These are reported results, not pins: the paper fixes no value for them.
+||x - x_oracle||_1 / ||x_oracle||_1.  Bars: FP64 1e-10; FP32 2e-5; BF16
+storage of every f array (8 significant bits at each of the 75 stage writes)
+2e-4 on rho and 1e-3 on u and T in the coupled run, 2e-3 on every field in
+the fully kinetic run.  (Rounding the oracle's own arrays to BF16 at the same
+points gives 1.2e-4 on rho in the coupled run: the bar is that error with a
+margin, and the GPU's error is of that size.)  These are reported results,
+not pins: the paper fixes no value for them.
 Setting ESBGK_REPORT_DIR writes the table there as JSON.
 """
 import json
@@ -88,7 +91,7 @@ def kinetic():
     return d, mask, run_oracle(d, 12, mask)
 
 
-BARS_COUPLED = {"fp64": (1e-10, 1e-10, 1e-10), "fp32": (2e-5, 2e-5, 2e-5), "bf16": (1e-4, 1e-3, 1e-3)}
+BARS_COUPLED = {"fp64": (1e-10, 1e-10, 1e-10), "fp32": (2e-5, 2e-5, 2e-5), "bf16": (2e-4, 1e-3, 1e-3)}
 BARS_KINETIC = {"fp64": (1e-10, 1e-10, 1e-10), "fp32": (2e-5, 2e-5, 2e-5), "bf16": (2e-3, 2e-3, 2e-3)}
 PRECISION = {"fp64": 0, "fp32": 1, "bf16": 2}
 
