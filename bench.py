@@ -37,8 +37,11 @@ WORKLOADS = {
     "blast": dict(gen="blast", nx=1024, nv=64, vmax=20.0, kw=dict(), steps=200),
 }
 
-# f-array passes (reads + writes) per point of each kinetic kernel class
-PASSES = {"stage2": 2, "stage3": 3, "final": 4}
+# f-array passes (reads + writes) per point of each kinetic kernel class:
+# (passes over state arrays f^n / f^{n+1}, passes over stage arrays f^(2), f^(3))
+PASSES = {"stage2": (1, 1), "stage3": (1, 2), "final": (2, 2)}
+# bytes per value of (state, stage) arrays
+ELEM = {"fp64": (8, 8), "fp32": (4, 4), "bf16": (2, 2), "mixed": (4, 2)}
 
 
 def kernel_source_digest():
@@ -76,7 +79,7 @@ def parse():
     ap.add_argument("--gpus", type=int, default=1)
     ap.add_argument("--steps", type=int, default=200)
     ap.add_argument("--warmup", type=int, default=10)
-    ap.add_argument("--precision", default="fp32", choices=["fp32", "bf16", "fp64"])
+    ap.add_argument("--precision", default="fp32", choices=["fp32", "bf16", "fp64", "mixed"])
     ap.add_argument("--workload", default="riemann4", choices=sorted(WORKLOADS))
     ap.add_argument("--no-cpu-baseline", action="store_true")
     ap.add_argument("--cpu-steps", type=int, default=16)
@@ -135,8 +138,8 @@ def main():
         del src, dst
 
     wl = WORKLOADS[args.workload]
-    prec = {"fp32": E.FP32, "bf16": E.BF16, "fp64": E.FP64}[args.precision]
-    esize = {"fp32": 4, "bf16": 2, "fp64": 8}[args.precision]
+    prec = {"fp32": E.FP32, "bf16": E.BF16, "fp64": E.FP64, "mixed": E.MIXED}[args.precision]
+    es_state, es_stage = ELEM[args.precision]
     nx, nv, vmax = wl["nx"], wl["nv"], wl["vmax"]
     d = getattr(inputs, wl["gen"])(nx=nx, ny=nx, nv=nv, vmax=vmax, **wl["kw"])
     cfg = E.make_config(nx, nx, nv, vmax, precision=prec, indicator=E.IND_PLAIN, scheme=E.ARS233,
@@ -168,7 +171,8 @@ def main():
     dom = max(range(3), key=lambda k: ms[k])
     kin_avg = kin_steps / max(args.steps, 1)
     t_launch = ms[dom] / max(launches[dom], 1) * 1e-3
-    bytes_launch = PASSES[names[dom]] * esize * kin_avg * nv * nv
+    ps, pg = PASSES[names[dom]]
+    bytes_launch = (ps * es_state + pg * es_stage) * kin_avg * nv * nv
     achieved = bytes_launch / t_launch / 1e9
     breakdown = {names[k]: round(ms[k] / max(launches[k], 1), 4) for k in range(3)}
     breakdown["fill"] = round(ms[3] / max(launches[3], 1), 4)
@@ -185,7 +189,8 @@ def main():
         "higher_is_better": True,
         "scaling": "weak",
         "vs_baseline": None,
-        "dtype": {"fp32": "f32", "bf16": "bf16-storage/f32", "fp64": "f64"}[args.precision],
+        "dtype": {"fp32": "f32", "bf16": "bf16-storage/f32", "fp64": "f64",
+                  "mixed": "f32-state/bf16-stages/f32"}[args.precision],
         "data": "synthetic",
         "config": {"workload": f"{wl['gen']} {nx}x{nx} cells x {nv}x{nv} velocities on [-{vmax:g},{vmax:g}]^2, "
                                f"ARS(2,3,3), minmod, regime update every step, {args.steps} steps from t=0",

@@ -49,7 +49,7 @@ extern "C" {
 /* ---- enumerations of esbgk_config fields */
 enum { ESBGK_ARS222 = 0, ESBGK_ARS233 = 1 };                  /* scheme */
 enum { ESBGK_UPWIND1 = 0, ESBGK_MINMOD2 = 1 };                /* recon */
-enum { ESBGK_FP64 = 0, ESBGK_FP32 = 1, ESBGK_BF16 = 2 };      /* precision of f */
+enum { ESBGK_FP64 = 0, ESBGK_FP32 = 1, ESBGK_BF16 = 2, ESBGK_MIXED = 3 }; /* precision of f */
 enum { ESBGK_IND_PLAIN = 0, ESBGK_IND_FROZEN = 1, ESBGK_IND_LEARNED = 2 }; /* indicator */
 enum { ESBGK_COUPLE_STAGE = 0, ESBGK_COUPLE_STEP = 1 };       /* coupling */
 
@@ -61,10 +61,12 @@ enum { ESBGK_COUPLE_STAGE = 0, ESBGK_COUPLE_STEP = 1 };       /* coupling */
  *              or minmod-limited piecewise linear; upwind flux for the
  *              kinetic transport (the Lax-Friedrichs flux of Sec. 3.2 with
  *              dissipation |v|), Rusanov flux for Euler.
- *  precision   storage and arithmetic of f: FP64; FP32; or BF16 storage
- *              with FP32 arithmetic.  Per-cell quantities are FP64 always,
- *              and so are the 2x2 ES-tensor algebra and the 6x6
- *              conservation solve.
+ *  precision   storage and arithmetic of f: FP64; FP32; BF16 storage with
+ *              FP32 arithmetic; or MIXED: the state f^n in FP32 and the two
+ *              intermediate stage arrays in BF16, FP32 arithmetic (ARS(2,3,3)
+ *              only).  FP32 velocity sums are compensated.  Per-cell
+ *              quantities are FP64 always, and so are the 2x2 ES-tensor
+ *              algebra and the 6x6 conservation solve.
  *  indicator   PLAIN: the breakdown criteria of Sec. 3.1.2 every step;
  *              FROZEN: the partition set by esbgk_set_mask() is kept (as in
  *              the order-of-accuracy test, Sec. 4.1.1); LEARNED: the MLP

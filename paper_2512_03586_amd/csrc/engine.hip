@@ -40,7 +40,9 @@ int fail(int code, const char *fmt, ...) {
 
 size_t align256(size_t x) { return (x + 255) & ~(size_t)255; }
 
-size_t elem_size(int precision) { return precision == ESBGK_FP64 ? 8 : precision == ESBGK_FP32 ? 4 : 2; }
+// bytes per value of the state arrays (f^n) and of the stage arrays (f^(2), f^(3))
+size_t state_elem(int precision) { return precision == ESBGK_FP64 ? 8 : precision == ESBGK_BF16 ? 2 : 4; }
+size_t stage_elem(int precision) { return precision == ESBGK_FP64 ? 8 : precision == ESBGK_FP32 ? 4 : 2; }
 
 // IMEX tableaux, 3 stages (Sec. 3.4.2 for ARS(2,3,3); ARS(2,2,2) its
 // second-order sibling).  Explicit (At, bt), implicit (A, b).
@@ -73,7 +75,9 @@ int validate(const esbgk_config *c) {
     if (c->nv < 4 || c->nv > 64 || c->nv % 4 != 0) return fail(ESBGK_EINVAL, "nv must be a multiple of 4 in [4, 64]");
     if (c->scheme != ESBGK_ARS222 && c->scheme != ESBGK_ARS233) return fail(ESBGK_EINVAL, "bad scheme");
     if (c->recon != ESBGK_UPWIND1 && c->recon != ESBGK_MINMOD2) return fail(ESBGK_EINVAL, "bad recon");
-    if (c->precision < ESBGK_FP64 || c->precision > ESBGK_BF16) return fail(ESBGK_EINVAL, "bad precision");
+    if (c->precision < ESBGK_FP64 || c->precision > ESBGK_MIXED) return fail(ESBGK_EINVAL, "bad precision");
+    if (c->precision == ESBGK_MIXED && c->scheme != ESBGK_ARS233)
+        return fail(ESBGK_EINVAL, "the mixed storage form needs ARS(2,3,3) (a separate final combination)");
     if (c->indicator != ESBGK_IND_PLAIN && c->indicator != ESBGK_IND_FROZEN && c->indicator != ESBGK_IND_LEARNED)
         return fail(ESBGK_EINVAL, "bad indicator mode");
     if (c->indicator == ESBGK_IND_LEARNED && c->learned_k < 1) return fail(ESBGK_EINVAL, "learned_k must be >= 1");
@@ -99,7 +103,7 @@ Layout layout(const esbgk_config *c) {
     const size_t nc = (size_t)c->nx * c->ny, nv2 = (size_t)c->nv * c->nv;
     size_t off = 0;
     auto take = [&](size_t bytes) { size_t o = off; off += align256(bytes); return o; };
-    for (int q = 0; q < 3; ++q) L.f[q] = take(nc * nv2 * elem_size(c->precision));
+    for (int q = 0; q < 3; ++q) L.f[q] = take(nc * nv2 * (q == 0 ? state_elem(c->precision) : stage_elem(c->precision)));
     for (int q = 0; q < 4; ++q) L.U[q] = take(4 * nc * sizeof(double));
     for (int q = 0; q < 2; ++q) L.gp[q] = take((size_t)GP_N * nc * sizeof(double));
     L.eps = take(nc * sizeof(double));
@@ -174,7 +178,7 @@ struct esbgk_ctx {
 
 namespace {
 
-template <class S> int run_step(esbgk_ctx *c, hipStream_t st);
+template <class SN, class SS> int run_step(esbgk_ctx *c, hipStream_t st);
 
 // Events bracketing one launch of kernel class k (only while timing is on).
 struct TimedLaunch {
@@ -244,34 +248,34 @@ IndicatorArgs indicator_args(const esbgk_config *cfg) {
 }
 
 // One IMEX stage (i = 1, 2) or the final combination (i = 3) on kinetic cells.
-template <class S> int kinetic_stage(esbgk_ctx *c, int i, hipStream_t st, double *Uout) {
-    StageArgs<S> a;
+template <class SN, class SS> int kinetic_stage(esbgk_ctx *c, int i, hipStream_t st, double *Uout) {
+    StageArgs a;
     memset(&a, 0, sizeof a);
     a.g = c->g;
-    a.fn = (const S *)c->f[0];
+    a.fn = c->f[0];
     const double *rowt = i < 3 ? &c->At[3 * i] : c->bt;
     const double *rowi = i < 3 ? &c->A[3 * i] : c->b;
     const int nprev = i < 3 ? i : 3;
     for (int j = 0; j < nprev; ++j)
-        if (rowt[j] != 0.0) { a.fl[a.nl] = (const S *)c->f[j]; a.cl[a.nl] = rowt[j]; ++a.nl; }
+        if (rowt[j] != 0.0) { a.fl[a.nl] = c->f[j]; a.cl[a.nl] = rowt[j]; ++a.nl; }
     for (int j = 1; j < nprev; ++j)
-        if (rowi[j] != 0.0) { a.fq[a.nq] = (const S *)c->f[j]; a.pq[a.nq] = c->gp[j - 1]; a.cq[a.nq] = rowi[j]; ++a.nq; }
+        if (rowi[j] != 0.0) { a.fq[a.nq] = c->f[j]; a.pq[a.nq] = c->gp[j - 1]; a.cq[a.nq] = rowi[j]; ++a.nq; }
     a.eps = c->eps; a.list = c->kin; a.count = c->counts; a.err = c->err; a.nc = c->nc;
     a.Uout = Uout;
     a.l1out = c->l1;
     if (i < 3) {
         a.aii = c->A[3 * i + i];
-        a.fout = (S *)c->f[i];
+        a.fout = c->f[i];
         a.pout = c->gp[i - 1];
         // ARS(2,2,2) is stiffly accurate: its last stage is f^{n+1}
         a.emit = (i == 2 && c->cfg.scheme == ESBGK_ARS222) ? 1 : 0;
     } else {
         a.aii = 0.0;
-        a.fout = (S *)c->f[0];  // in place: the final kernel reads f^n only at its own cell
+        a.fout = c->f[0];  // in place: the final kernel reads f^n only at its own cell
         a.emit = 1;
     }
     TimedLaunch tl(c, i == 1 ? ESBGK_K_STAGE2 : i == 2 ? ESBGK_K_STAGE3 : ESBGK_K_FINAL, st);
-    HIPCHK(launch_stage<S>(a, c->nc, st));
+    HIPCHK((launch_stage<SN, SS>(a, c->nc, st)));
     HIPCHK(tl.done());
     return ESBGK_OK;
 }
@@ -320,7 +324,7 @@ int learned_update(esbgk_ctx *c, hipStream_t st) {
     return ESBGK_OK;
 }
 
-template <class S> int run_step(esbgk_ctx *c, hipStream_t st) {
+template <class SN, class SS> int run_step(esbgk_ctx *c, hipStream_t st) {
     const size_t nc = (size_t)c->nc;
     const bool loc = c->cfg.coupling == ESBGK_COUPLE_STEP;
     int rc;
@@ -333,15 +337,15 @@ template <class S> int run_step(esbgk_ctx *c, hipStream_t st) {
         HIPCHK(launch_indicator(ia, st));
         if ((rc = regime_lists(c, c->mask_old, st))) return rc;
         // fluid -> kinetic: f = Mhat(U) (eq. Coupling_FluKin); kinetic -> fluid keeps U = moments(f)
-        if ((rc = fill_list<S>(c, c->f[0], c->U[0], c->newk, c->counts + 2, st))) return rc;
+        if ((rc = fill_list<SN>(c, c->f[0], c->U[0], c->newk, c->counts + 2, st))) return rc;
     } else if (c->cfg.indicator == ESBGK_IND_LEARNED && c->steps % c->cfg.learned_k == 0) {
         if ((rc = learned_update(c, st))) return rc;
         if ((rc = regime_lists(c, c->mask_old, st))) return rc;
-        if ((rc = fill_list<S>(c, c->f[0], c->U[0], c->newk, c->counts + 2, st))) return rc;
+        if ((rc = fill_list<SN>(c, c->f[0], c->U[0], c->newk, c->counts + 2, st))) return rc;
     }
     HIPCHK(launch_accumulate_count(c->counts, c->kin_total, st));
     // ---- stage 1 coupling: buffer cells carry Mhat(U^n)
-    if ((rc = fill_list<S>(c, c->f[0], c->U[0], c->buf, c->counts + 1, st))) return rc;
+    if ((rc = fill_list<SN>(c, c->f[0], c->U[0], c->buf, c->counts + 1, st))) return rc;
     // ---- stages 2 and 3
     for (int i = 1; i <= 2; ++i) {
         const bool last222 = (i == 2 && c->cfg.scheme == ESBGK_ARS222);
@@ -351,16 +355,16 @@ template <class S> int run_step(esbgk_ctx *c, hipStream_t st) {
             HIPCHK(hipMemcpyAsync(c->U[i], c->U[0], 4 * nc * sizeof(double), hipMemcpyDeviceToDevice, st));
             if (!last222) Ukin = c->U[3];
         }
-        if ((rc = kinetic_stage<S>(c, i, st, Ukin))) return rc;
+        if ((rc = kinetic_stage<SN, SS>(c, i, st, Ukin))) return rc;
         if ((rc = euler_stage(c, i, st, c->U[i]))) return rc;
         if (!last222) {
             const double *Ub = loc ? c->U[0] : c->U[i];
-            if ((rc = fill_list<S>(c, c->f[i], Ub, c->buf, c->counts + 1, st))) return rc;
+            if ((rc = fill_list<SS>(c, c->f[i], Ub, c->buf, c->counts + 1, st))) return rc;
         }
     }
     if (c->cfg.scheme == ESBGK_ARS233) {
         // ---- final combination (eq. RKEI2 / RKEuler_2), then coupling of U^{n+1}
-        if ((rc = kinetic_stage<S>(c, 3, st, c->U[3]))) return rc;
+        if ((rc = kinetic_stage<SN, SS>(c, 3, st, c->U[3]))) return rc;
         if ((rc = euler_stage(c, 3, st, c->U[3]))) return rc;
         std::swap(c->U[0], c->U[3]);
     } else {
@@ -506,8 +510,8 @@ int esbgk_set_mask(esbgk_ctx *c, const uint8_t *d_mask, void *stream) {
     hipStream_t st = (hipStream_t)stream;
     switch (c->cfg.precision) {
         case ESBGK_FP64: return set_mask_impl<double>(c, d_mask, st);
-        case ESBGK_FP32: return set_mask_impl<float>(c, d_mask, st);
-        default: return set_mask_impl<bf16_t>(c, d_mask, st);
+        case ESBGK_BF16: return set_mask_impl<bf16_t>(c, d_mask, st);
+        default: return set_mask_impl<float>(c, d_mask, st);
     }
 }
 
@@ -519,8 +523,8 @@ int esbgk_set_f(esbgk_ctx *c, const double *d_f, void *stream) {
     hipStream_t st = (hipStream_t)stream;
     switch (c->cfg.precision) {
         case ESBGK_FP64: return set_f_impl<double>(c, d_f, st);
-        case ESBGK_FP32: return set_f_impl<float>(c, d_f, st);
-        default: return set_f_impl<bf16_t>(c, d_f, st);
+        case ESBGK_BF16: return set_f_impl<bf16_t>(c, d_f, st);
+        default: return set_f_impl<float>(c, d_f, st);
     }
 }
 
@@ -532,9 +536,10 @@ int esbgk_step(esbgk_ctx *c, int nsteps, void *stream) {
     for (int n = 0; n < nsteps; ++n) {
         int rc;
         switch (c->cfg.precision) {
-            case ESBGK_FP64: rc = run_step<double>(c, st); break;
-            case ESBGK_FP32: rc = run_step<float>(c, st); break;
-            default: rc = run_step<bf16_t>(c, st); break;
+            case ESBGK_FP64: rc = run_step<double, double>(c, st); break;
+            case ESBGK_FP32: rc = run_step<float, float>(c, st); break;
+            case ESBGK_BF16: rc = run_step<bf16_t, bf16_t>(c, st); break;
+            default: rc = run_step<float, bf16_t>(c, st); break;
         }
         if (rc) return rc;
         c->steps += 1;
@@ -574,8 +579,8 @@ int esbgk_get_f(esbgk_ctx *c, double *d_f, void *stream) {
     hipStream_t st = (hipStream_t)stream;
     switch (c->cfg.precision) {
         case ESBGK_FP64: HIPCHK(launch_to_f64<double>(c->f[0], d_f, n, st)); break;
-        case ESBGK_FP32: HIPCHK(launch_to_f64<float>(c->f[0], d_f, n, st)); break;
-        default: HIPCHK(launch_to_f64<bf16_t>(c->f[0], d_f, n, st)); break;
+        case ESBGK_BF16: HIPCHK(launch_to_f64<bf16_t>(c->f[0], d_f, n, st)); break;
+        default: HIPCHK(launch_to_f64<float>(c->f[0], d_f, n, st)); break;
     }
     return ESBGK_OK;
 }

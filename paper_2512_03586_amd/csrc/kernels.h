@@ -5,15 +5,19 @@
 
 namespace esbgk {
 
-template <class S> struct StageArgs {
+// Arrays of f are of the state's storage type SN (f^n, and f^{n+1} written by
+// the final combination) or of the stage arrays' type SS (f^(2), f^(3)); the
+// kernels cast them.  The first transported array of an implicit stage is
+// f^n, every other transported array is a stage array.
+struct StageArgs {
     Geom g;
-    const S *fn;                                        // f^n: base value at the cell
-    const S *fl[2]; double cl[2];                       // transport terms  -dt*cl*L(fl)
-    const S *fq[2]; const double *pq[2]; double cq[2];  // sources +dt*cq*(tau/eps)(Ghat-fq)
+    const void *fn;                                        // f^n: base value at the cell
+    const void *fl[2]; double cl[2];                       // transport terms  -dt*cl*L(fl)
+    const void *fq[2]; const double *pq[2]; double cq[2];  // sources +dt*cq*(tau/eps)(Ghat-fq)
     int nl, nq;
-    double aii;                                         // implicit coefficient; 0 -> final combination
-    int emit;                                           // write the L1 distance of the result
-    S *fout;
+    double aii;                                            // implicit coefficient; 0 -> final combination
+    int emit;                                              // write the L1 distance of the result
+    void *fout;
     double *pout;                                       // Gaussian parameters (GP_N per cell)
     double *Uout;                                       // SoA [4][nc]
     double *l1out;
@@ -70,7 +74,7 @@ struct IndicatorArgs {
     double *lambda;
 };
 
-template <class S> hipError_t launch_stage(const StageArgs<S> &a, int nmax, hipStream_t st);
+template <class SN, class SS> hipError_t launch_stage(const StageArgs &a, int nmax, hipStream_t st);
 template <class S> hipError_t launch_fill(const FillArgs<S> &a, int nmax, hipStream_t st);
 template <class S> hipError_t launch_moments(const MomArgs<S> &a, int nmax, hipStream_t st);
 template <class S> hipError_t launch_from_f64(const double *in, void *out, size_t n, hipStream_t st);

@@ -19,6 +19,8 @@
 // its moments U^{n+1} and the L1 distance to the Maxwellian that the next
 // regime update reads (eq. eqKintoFluid1).
 #pragma once
+#include <type_traits>
+
 #include "kernels.h"
 
 // implicit stages: stencil loads of the next work unit issued before the
@@ -461,10 +463,11 @@ __device__ inline void gaussian_pass(T (&glds)[C][64][4], T (*vlds)[64][4], int 
 // the square of the quadrature error, far below the arithmetic's rounding.
 template <class T> __device__ constexpr double correction_tol() { return sizeof(T) == 8 ? 1e-9 : 1e-6; }
 
-template <class S, int NV, int L, int C, int NL, int NQ, bool FINAL, int RECON>
-__global__ __launch_bounds__((64 * waves_per_block<typename Storage<S>::T, C>()), ESBGK_STAGE_MIN_WAVES) void stage_kernel(
-    StageArgs<S> a) {
-    using T = typename Storage<S>::T;
+template <class SN, class SS, int NV, int L, int C, int NL, int NQ, bool FINAL, int RECON>
+__global__ __launch_bounds__((64 * waves_per_block<typename Storage<SN>::T, C>()), ESBGK_STAGE_MIN_WAVES) void stage_kernel(
+    StageArgs a) {
+    using T = typename Storage<SN>::T;
+    static_assert(std::is_same<T, typename Storage<SS>::T>::value, "one arithmetic type per kernel");
     __shared__ StageLds<T, C> lds;
     const Geom &g = a.g;
     const GroupCell gc = group_cell<L, waves_per_block<T, C>()>(a.list, *a.count);
@@ -497,8 +500,11 @@ __global__ __launch_bounds__((64 * waves_per_block<typename Storage<S>::T, C>())
         const int m = u / NL, l = u % NL;
         const Chunk<T> ch = chunk_of<T, L, NV>(s, m, g);
         if (!ch.active) return;
-        load_stencil<S, RECON>(a.fl[l], nb, ch, sb[slot]);
-        if (FINAL && l == 0) Storage<S>::load4(a.fn + nb.c, (uint32_t)ch.k0, sb[slot].b);
+        if (!FINAL && l == 0)
+            load_stencil<SN, RECON>((const SN *)a.fl[0], nb, ch, sb[slot]);
+        else
+            load_stencil<SS, RECON>((const SS *)a.fl[l], nb, ch, sb[slot]);
+        if (FINAL && l == 0) Storage<SN>::load4((const SN *)a.fn + nb.c, (uint32_t)ch.k0, sb[slot].b);
     };
     if (PF) load_unit(0, 0);
 #pragma unroll
@@ -543,7 +549,7 @@ __global__ __launch_bounds__((64 * waves_per_block<typename Storage<S>::T, C>())
                 macc.add(ch, fs);
 #pragma unroll
                 for (int e = 0; e < 4; ++e) lds.v[wave][m][lane][e] = fs[e];
-                if (FINAL && gc.valid) Storage<S>::store4(a.fout + nb.c, (uint32_t)ch.k0, fs);
+                if (FINAL && gc.valid) Storage<SN>::store4((SN *)a.fout + nb.c, (uint32_t)ch.k0, fs);
             }
         }
         if (l == NL - 1 && (m & 3) == 3) macc.fold();
@@ -605,7 +611,7 @@ __global__ __launch_bounds__((64 * waves_per_block<typename Storage<S>::T, C>())
                     const T Ghat = lds.g[wave][m][lane][e] * ((T)1 + ((d3 * aa + plin) * aa + pconst));
                     fv[e] = (lds.v[wave][m][lane][e] + lamt * Ghat) * inv1;
                 }
-                if (gc.valid) Storage<S>::store4(a.fout + nb.c, (uint32_t)ch.k0, fv);
+                if (gc.valid) Storage<SS>::store4((SS *)a.fout + nb.c, (uint32_t)ch.k0, fv);
                 if (want_l1) {
                     const T ey = ch.vy - uyt, qy = mq * ey * ey;
 #pragma unroll
@@ -793,17 +799,17 @@ static inline unsigned grid_for(int nmax, int cells_per_block) {
 #define ESBGK_STATIC_NV(X) X(16, 16, 4) X(32, ESBGK_NV32_L, ESBGK_NV32_C) X(48, 64, 9) X(64, 64, 16)
 #define ESBGK_SHAPES(X) X(0, 16, 4) X(0, 16, 8) X(0, 32, 8) X(0, 64, 9) X(0, 64, 16)
 
-template <class S, int NL, int NQ, bool FINAL>
-static hipError_t stage_dispatch(const StageArgs<S> &a, int nmax, hipStream_t st) {
+template <class SN, class SS, int NL, int NQ, bool FINAL>
+static hipError_t stage_dispatch(const StageArgs &a, int nmax, hipStream_t st) {
     const Shape sh = shape_for(a.g.nv2);
 #define ESBGK_CASE(NN, LL, CC)                                                                                     \
     if ((NN == 0) ? (sh.L == LL && sh.C == CC) : (a.g.nv == NN)) {                                                    \
-        constexpr int WPB = waves_per_block<typename Storage<S>::T, CC>();                                                                  \
+        constexpr int WPB = waves_per_block<typename Storage<SN>::T, CC>();                                         \
         const dim3 grid(grid_for(nmax, WPB * (64 / LL))), block(64 * WPB);                                          \
         if (a.g.recon == 0)                                                                                         \
-            hipLaunchKernelGGL((stage_kernel<S, NN, LL, CC, NL, NQ, FINAL, 0>), grid, block, 0, st, a);             \
+            hipLaunchKernelGGL((stage_kernel<SN, SS, NN, LL, CC, NL, NQ, FINAL, 0>), grid, block, 0, st, a);        \
         else                                                                                                        \
-            hipLaunchKernelGGL((stage_kernel<S, NN, LL, CC, NL, NQ, FINAL, 1>), grid, block, 0, st, a);             \
+            hipLaunchKernelGGL((stage_kernel<SN, SS, NN, LL, CC, NL, NQ, FINAL, 1>), grid, block, 0, st, a);        \
         return hipGetLastError();                                                                                   \
     }
     ESBGK_STATIC_NV(ESBGK_CASE)
@@ -812,17 +818,17 @@ static hipError_t stage_dispatch(const StageArgs<S> &a, int nmax, hipStream_t st
     return hipErrorInvalidValue;
 }
 
-template <class S>
-hipError_t launch_stage(const StageArgs<S> &a, int nmax, hipStream_t st) {
+template <class SN, class SS>
+hipError_t launch_stage(const StageArgs &a, int nmax, hipStream_t st) {
     // the kernels take the implicit terms' states from the last NQ transported arrays
     for (int q = 0; q < a.nq; ++q)
         if (a.nl - a.nq + q < 0 || a.fq[q] != a.fl[a.nl - a.nq + q]) return hipErrorInvalidValue;
     if (a.aii > 0.0) {
         if (a.nl < 1 || a.fl[0] != a.fn) return hipErrorInvalidValue;  // implicit stages transport f^n first
-        if (a.nl == 1 && a.nq == 0) return stage_dispatch<S, 1, 0, false>(a, nmax, st);
-        if (a.nl == 2 && a.nq == 1) return stage_dispatch<S, 2, 1, false>(a, nmax, st);
+        if (a.nl == 1 && a.nq == 0) return stage_dispatch<SN, SS, 1, 0, false>(a, nmax, st);
+        if (a.nl == 2 && a.nq == 1) return stage_dispatch<SN, SS, 2, 1, false>(a, nmax, st);
     } else {
-        if (a.nl == 2 && a.nq == 2) return stage_dispatch<S, 2, 2, true>(a, nmax, st);
+        if (a.nl == 2 && a.nq == 2) return stage_dispatch<SN, SS, 2, 2, true>(a, nmax, st);
     }
     return hipErrorInvalidValue;
 }
@@ -876,8 +882,9 @@ hipError_t launch_to_f64(const void *in, double *out, size_t n, hipStream_t st) 
     return hipGetLastError();
 }
 
+#define ESBGK_INST_STAGE(SN, SS) template hipError_t launch_stage<SN, SS>(const StageArgs &, int, hipStream_t);
 #define ESBGK_INST(S)                                                                        \
-    template hipError_t launch_stage<S>(const StageArgs<S> &, int, hipStream_t);             \
+    ESBGK_INST_STAGE(S, S)                                                                   \
     template hipError_t launch_fill<S>(const FillArgs<S> &, int, hipStream_t);               \
     template hipError_t launch_moments<S>(const MomArgs<S> &, int, hipStream_t);             \
     template hipError_t launch_from_f64<S>(const double *, void *, size_t, hipStream_t);     \

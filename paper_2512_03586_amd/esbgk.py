@@ -19,7 +19,7 @@ LIB_PATH = os.environ.get("ESBGK_LIB", os.path.join(_HERE, "libesbgk.so"))
 OK, EINVAL, ENOMEM, EDEVICE, ENONPHYS = 0, -1, -2, -3, -4
 ARS222, ARS233 = 0, 1
 UPWIND1, MINMOD2 = 0, 1
-FP64, FP32, BF16 = 0, 1, 2
+FP64, FP32, BF16, MIXED = 0, 1, 2, 3
 IND_PLAIN, IND_FROZEN, IND_LEARNED = 0, 1, 2
 COUPLE_STAGE, COUPLE_STEP = 0, 1
 

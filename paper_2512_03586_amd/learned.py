@@ -161,9 +161,10 @@ def dilation_radius(K, cfl=0.5):
 
 def run(mode, d, *, nx, nv, vmax, steps, K=10, precision=E.FP32, net=None, threshold=0.0, dilation=0,
         timed=False):
-    """One run; mode 'plain', 'learned' or 'dilated'.  Returns a dict of
+    """One run; mode 'plain', 'learned', 'dilated' or 'kinetic' (every cell
+    kinetic throughout, the reference of the hybrid).  Returns a dict of
     results (primitives at the end, kinetic cell-steps, judge counters, time)."""
-    ind = E.IND_PLAIN if mode == "plain" else E.IND_LEARNED
+    ind = {"plain": E.IND_PLAIN, "kinetic": E.IND_FROZEN}.get(mode, E.IND_LEARNED)
     cfg = E.make_config(nx, nx, nv, vmax, precision=precision, indicator=ind, scheme=E.ARS233, recon=E.MINMOD2,
                         eta=1e-2, delta=1e-3, learned_k=K)
     eng = E.Engine(cfg)
@@ -172,6 +173,8 @@ def run(mode, d, *, nx, nv, vmax, steps, K=10, precision=E.FP32, net=None, thres
     elif mode == "dilated":
         eng.set_learned(None, 0.0, dilation)
     eng.set_state(d["rho"], d["ux"], d["uy"], d["T"], d["eps"])
+    if mode == "kinetic":
+        eng.set_mask(np.ones(nx * nx, np.uint8))
     torch.cuda.synchronize()
     t0 = time.perf_counter()
     eng.step(steps)
@@ -180,6 +183,6 @@ def run(mode, d, *, nx, nv, vmax, steps, K=10, precision=E.FP32, net=None, thres
     st = eng.stats()
     out = dict(prim=np.stack([t.cpu().numpy() for t in eng.moments()]), kinetic_cell_steps=int(st.kinetic_cell_steps),
                seconds=el, mask=eng.mask().cpu().numpy())
-    if mode != "plain":
+    if mode in ("learned", "dilated"):
         out["judge"] = eng.learned_stats()
     return out

@@ -62,6 +62,9 @@ def test_workspace_size_is_pure_and_scales(E):
     (dict(beta=1.0), "beta"),
     (dict(scheme=7), "scheme"),
     (dict(eta=0.0), "eta"),
+    (dict(precision=3, scheme=0), "mixed storage form needs ARS"),
+    (dict(precision=4), "precision"),
+    (dict(indicator=2, learned_k=0), "learned_k"),
 ])
 def test_bad_configs_are_rejected(E, kw, msg):
     base = dict(nx=8, ny=8, nv=16, vmax=8.0)

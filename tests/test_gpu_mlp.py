@@ -154,8 +154,10 @@ def test_learned_mode_counters_and_fallback():
 def test_trained_indicator_gains_over_dilated_plain_every_k():
     """Trained on plain runs of the four-quadrant generator, the network keeps
     fewer kinetic cell-steps than the plain-every-K baseline with dilation by
-    ceil(K CFL sqrt 2) cells, at a small missed-cell rate and a density error
-    against the plain-every-step run of the same size as the baseline's."""
+    ceil(K CFL sqrt 2) cells, at a small missed-cell rate.  Solution error of
+    each mask policy is measured against the fully kinetic run (every cell
+    kinetic, the model the hybrid approximates): the learned run stays within
+    the plain-every-step method's own error."""
     kw = dict(nx=96, nv=16, vmax=10.0, steps=100, K=10)
     train = L.collect(range(0, 6), **kw)
     val = L.collect(range(100, 102), **kw)
@@ -166,14 +168,18 @@ def test_trained_indicator_gains_over_dilated_plain_every_k():
     lrn = L.run("learned", d, net=net, threshold=res.threshold, **common)
     dil = L.run("dilated", d, dilation=L.dilation_radius(10), **common)
 
-    def rho_err(r):
-        return float(np.abs(r["prim"][0] - plain["prim"][0]).sum() / np.abs(plain["prim"][0]).sum())
+    full = L.run("kinetic", d, nx=96, nv=16, vmax=10.0, steps=100)
+
+    def rho_err(r, ref):
+        return float(np.abs(r["prim"][0] - ref["prim"][0]).sum() / np.abs(ref["prim"][0]).sum())
 
     nc = 96 * 96
     checks, missed, extra, _ = lrn["judge"]
     miss_rate = missed / (checks * nc)
-    print("plain", plain["kinetic_cell_steps"], "learned", lrn["kinetic_cell_steps"], "dilated",
-          dil["kinetic_cell_steps"], "miss rate", miss_rate, "err", rho_err(lrn), rho_err(dil), res)
+    e_plain, e_lrn, e_dil = rho_err(plain, full), rho_err(lrn, full), rho_err(dil, full)
+    print("kinetic cell-steps: plain", plain["kinetic_cell_steps"], "learned", lrn["kinetic_cell_steps"],
+          "dilated", dil["kinetic_cell_steps"], "| miss rate", miss_rate, "| rho error vs fully kinetic: plain",
+          e_plain, "learned", e_lrn, "dilated", e_dil, "| learned vs plain", rho_err(lrn, plain), res)
     assert lrn["kinetic_cell_steps"] < 0.9 * dil["kinetic_cell_steps"]
     assert miss_rate <= 5e-3
-    assert rho_err(lrn) <= max(2 * rho_err(dil), 1e-4)
+    assert e_lrn <= 1.05 * e_plain
