@@ -38,10 +38,11 @@ WORKLOADS = {
 }
 
 # f-array passes (reads + writes) per point of each kinetic kernel class:
-# (passes over state arrays f^n / f^{n+1}, passes over stage arrays f^(2), f^(3))
-PASSES = {"stage2": (1, 1), "stage3": (1, 2), "final": (2, 2)}
-# bytes per value of (state, stage) arrays
-ELEM = {"fp64": (8, 8), "fp32": (4, 4), "bf16": (2, 2), "mixed": (4, 2)}
+# (state arrays f^n / f^{n+1}, stage arrays f^(2), f^(3), partial sum P).  The
+# last implicit stage writes P, the final combination reads P and f^(3).
+PASSES = {"stage2": (1, 1, 0), "stage3": (1, 2, 1), "final": (1, 1, 1)}
+# bytes per value of (state, stage, partial) arrays
+ELEM = {"fp64": (8, 8, 8), "fp32": (4, 4, 4), "bf16": (2, 2, 4), "mixed": (4, 2, 4)}
 
 
 def kernel_source_digest():
@@ -139,7 +140,7 @@ def main():
 
     wl = WORKLOADS[args.workload]
     prec = {"fp32": E.FP32, "bf16": E.BF16, "fp64": E.FP64, "mixed": E.MIXED}[args.precision]
-    es_state, es_stage = ELEM[args.precision]
+    es = ELEM[args.precision]
     nx, nv, vmax = wl["nx"], wl["nv"], wl["vmax"]
     d = getattr(inputs, wl["gen"])(nx=nx, ny=nx, nv=nv, vmax=vmax, **wl["kw"])
     cfg = E.make_config(nx, nx, nv, vmax, precision=prec, indicator=E.IND_PLAIN, scheme=E.ARS233,
@@ -171,8 +172,7 @@ def main():
     dom = max(range(3), key=lambda k: ms[k])
     kin_avg = kin_steps / max(args.steps, 1)
     t_launch = ms[dom] / max(launches[dom], 1) * 1e-3
-    ps, pg = PASSES[names[dom]]
-    bytes_launch = (ps * es_state + pg * es_stage) * kin_avg * nv * nv
+    bytes_launch = sum(n * b for n, b in zip(PASSES[names[dom]], es)) * kin_avg * nv * nv
     achieved = bytes_launch / t_launch / 1e9
     breakdown = {names[k]: round(ms[k] / max(launches[k], 1), 4) for k in range(3)}
     breakdown["fill"] = round(ms[3] / max(launches[3], 1), 4)

@@ -91,7 +91,7 @@ int validate(const esbgk_config *c) {
 }
 
 struct Layout {
-    size_t f[3], U[4], gp[2], eps, l1, prim, mask, mask_old, cls, kin, buf, newk, blockcounts, counts, err,
+    size_t f[3], fP, U[4], gp[2], eps, l1, prim, mask, mask_old, cls, kin, buf, newk, blockcounts, counts, err,
         bad, kin_total;
     // learned indicator (indicator == LEARNED only)
     size_t fields, derived, X, samples, logits, pmask, lcount;
@@ -104,6 +104,8 @@ Layout layout(const esbgk_config *c) {
     size_t off = 0;
     auto take = [&](size_t bytes) { size_t o = off; off += align256(bytes); return o; };
     for (int q = 0; q < 3; ++q) L.f[q] = take(nc * nv2 * (q == 0 ? state_elem(c->precision) : stage_elem(c->precision)));
+    // partial sum of the final combination (ARS(2,3,3)), state precision and at least FP32
+    L.fP = take(c->scheme == ESBGK_ARS233 ? nc * nv2 * std::max<size_t>(4, state_elem(c->precision)) : 0);
     for (int q = 0; q < 4; ++q) L.U[q] = take(4 * nc * sizeof(double));
     for (int q = 0; q < 2; ++q) L.gp[q] = take((size_t)GP_N * nc * sizeof(double));
     L.eps = take(nc * sizeof(double));
@@ -146,6 +148,7 @@ struct esbgk_ctx {
     double At[9]{}, bt[3]{}, A[9]{}, b[3]{};
     char *ws = nullptr;
     void *f[3]{};
+    void *fP = nullptr;
     double *U[4]{};
     double *gp[2]{};
     double *eps = nullptr, *l1 = nullptr, *prim = nullptr;
@@ -248,30 +251,45 @@ IndicatorArgs indicator_args(const esbgk_config *cfg) {
 }
 
 // One IMEX stage (i = 1, 2) or the final combination (i = 3) on kinetic cells.
+// One IMEX stage (i = 1, 2) or the final combination (i = 3) on kinetic cells.
+// With ARS(2,3,3) the last implicit stage also writes the partial sum
+//   P = f^n - dt sum_{j<3} bt_j L(f^(j)) + dt sum_{j<3} b_j Q'_j
+// (its transport and implicit terms are the ones the stage computes anyway),
+// and the final combination is f^{n+1} = P - dt bt_3 L(f^(3)) + dt b_3 Q'_3.
 template <class SN, class SS> int kinetic_stage(esbgk_ctx *c, int i, hipStream_t st, double *Uout) {
     StageArgs a;
     memset(&a, 0, sizeof a);
     a.g = c->g;
-    a.fn = c->f[0];
-    const double *rowt = i < 3 ? &c->At[3 * i] : c->bt;
-    const double *rowi = i < 3 ? &c->A[3 * i] : c->b;
-    const int nprev = i < 3 ? i : 3;
-    for (int j = 0; j < nprev; ++j)
-        if (rowt[j] != 0.0) { a.fl[a.nl] = c->f[j]; a.cl[a.nl] = rowt[j]; ++a.nl; }
-    for (int j = 1; j < nprev; ++j)
-        if (rowi[j] != 0.0) { a.fq[a.nq] = c->f[j]; a.pq[a.nq] = c->gp[j - 1]; a.cq[a.nq] = rowi[j]; ++a.nq; }
     a.eps = c->eps; a.list = c->kin; a.count = c->counts; a.err = c->err; a.nc = c->nc;
     a.Uout = Uout;
     a.l1out = c->l1;
+    const bool partial = c->cfg.scheme == ESBGK_ARS233;
     if (i < 3) {
+        a.fn = c->f[0];
+        const double *rowt = &c->At[3 * i], *rowi = &c->A[3 * i];
+        for (int j = 0; j < i; ++j)
+            if (rowt[j] != 0.0 || (partial && i == 2 && c->bt[j] != 0.0)) {
+                a.fl[a.nl] = c->f[j]; a.cl[a.nl] = rowt[j]; a.scl[a.nl] = c->bt[j]; ++a.nl;
+            }
+        for (int j = 1; j < i; ++j)
+            if (rowi[j] != 0.0) { a.fq[a.nq] = c->f[j]; a.pq[a.nq] = c->gp[j - 1]; a.cq[a.nq] = rowi[j]; ++a.nq; }
         a.aii = c->A[3 * i + i];
         a.fout = c->f[i];
         a.pout = c->gp[i - 1];
+        if (partial && i == 2) {
+            // the one implicit term of stage 3 is that of stage 2
+            if (a.nq != 1 || c->b[0] != 0.0) return fail(ESBGK_EINVAL, "tableau not supported by the partial sum");
+            a.sout = c->fP;
+            a.scq = c->b[1];
+        }
         // ARS(2,2,2) is stiffly accurate: its last stage is f^{n+1}
         a.emit = (i == 2 && c->cfg.scheme == ESBGK_ARS222) ? 1 : 0;
     } else {
+        a.fn = c->fP;
+        a.fl[0] = c->f[2]; a.cl[0] = c->bt[2]; a.nl = 1;
+        a.fq[0] = c->f[2]; a.pq[0] = c->gp[1]; a.cq[0] = c->b[2]; a.nq = 1;
         a.aii = 0.0;
-        a.fout = c->f[0];  // in place: the final kernel reads f^n only at its own cell
+        a.fout = c->f[0];  // f^n is not read by the final combination
         a.emit = 1;
     }
     TimedLaunch tl(c, i == 1 ? ESBGK_K_STAGE2 : i == 2 ? ESBGK_K_STAGE3 : ESBGK_K_FINAL, st);
@@ -441,6 +459,7 @@ int esbgk_create(const esbgk_config *cfg, void *d_workspace, size_t bytes, esbgk
     char *w = (char *)d_workspace;
     c->ws = w;
     for (int q = 0; q < 3; ++q) c->f[q] = w + L.f[q];
+    c->fP = w + L.fP;
     for (int q = 0; q < 4; ++q) c->U[q] = (double *)(w + L.U[q]);
     for (int q = 0; q < 2; ++q) c->gp[q] = (double *)(w + L.gp[q]);
     c->eps = (double *)(w + L.eps);

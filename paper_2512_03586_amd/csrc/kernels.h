@@ -18,6 +18,9 @@ struct StageArgs {
     double aii;                                            // implicit coefficient; 0 -> final combination
     int emit;                                              // write the L1 distance of the result
     void *fout;
+    // side output of an implicit stage (state type, at least FP32): P = fn - dt sum_l scl[l] L(fl[l])
+    // + dt scq (tau/eps)(Ghat - fq[0]); the final combination reads it as its base
+    void *sout; double scl[2]; double scq;
     double *pout;                                       // Gaussian parameters (GP_N per cell)
     double *Uout;                                       // SoA [4][nc]
     double *l1out;

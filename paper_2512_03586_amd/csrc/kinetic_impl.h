@@ -29,9 +29,13 @@
 #define ESBGK_PREFETCH 1
 #endif
 
-// waves per SIMD the stage kernels are compiled for (caps their VGPR budget)
+// waves per SIMD the stage kernels are compiled for (caps their VGPR budget):
+// implicit stages, final combination
 #ifndef ESBGK_STAGE_MIN_WAVES
 #define ESBGK_STAGE_MIN_WAVES 3
+#endif
+#ifndef ESBGK_FINAL_MIN_WAVES
+#define ESBGK_FINAL_MIN_WAVES 4
 #endif
 
 namespace esbgk {
@@ -463,10 +467,17 @@ __device__ inline void gaussian_pass(T (&glds)[C][64][4], T (*vlds)[64][4], int 
 // the square of the quadrature error, far below the arithmetic's rounding.
 template <class T> __device__ constexpr double correction_tol() { return sizeof(T) == 8 ? 1e-9 : 1e-6; }
 
-template <class SN, class SS, int NV, int L, int C, int NL, int NQ, bool FINAL, int RECON>
-__global__ __launch_bounds__((64 * waves_per_block<typename Storage<SN>::T, C>()), ESBGK_STAGE_MIN_WAVES) void stage_kernel(
+// Storage of the partial sum P of the final combination: at least FP32 (it is
+// a state-like quantity, rounded into f^{n+1}).
+template <class S> struct PartialOf { using type = S; };
+template <> struct PartialOf<bf16_t> { using type = float; };
+
+template <class SN, class SS, int NV, int L, int C, int NL, int NQ, bool FINAL, int RECON, bool SIDE>
+__global__ __launch_bounds__((64 * waves_per_block<typename Storage<SN>::T, C>()),
+                             (FINAL ? ESBGK_FINAL_MIN_WAVES : ESBGK_STAGE_MIN_WAVES)) void stage_kernel(
     StageArgs a) {
     using T = typename Storage<SN>::T;
+    using SP = typename PartialOf<SN>::type;
     static_assert(std::is_same<T, typename Storage<SS>::T>::value, "one arithmetic type per kernel");
     __shared__ StageLds<T, C> lds;
     const Geom &g = a.g;
@@ -492,10 +503,11 @@ __global__ __launch_bounds__((64 * waves_per_block<typename Storage<SN>::T, C>()
     // launcher checks this), so their values are the stencil centres.
     MomentAcc<T> macc;
     constexpr int NU = C * NL;
-    constexpr bool PF = ESBGK_PREFETCH != 0 && !FINAL;  // the final kernel would spill
+    constexpr bool PF = ESBGK_PREFETCH != 0;
     constexpr int NB = PF ? 2 : 1;
     Stencil<T> sb[NB];
-    T base[4], acc[4], qsum[4];  // base: f^n at the cell
+    T base[4], acc[4], qsum[4];  // base: f^n at the cell (final combination: the partial sum P)
+    T pacc[4], psum[4];          // side output P of the last implicit stage
     auto load_unit = [&](int u, int slot) {
         const int m = u / NL, l = u % NL;
         const Chunk<T> ch = chunk_of<T, L, NV>(s, m, g);
@@ -504,7 +516,7 @@ __global__ __launch_bounds__((64 * waves_per_block<typename Storage<SN>::T, C>()
             load_stencil<SN, RECON>((const SN *)a.fl[0], nb, ch, sb[slot]);
         else
             load_stencil<SS, RECON>((const SS *)a.fl[l], nb, ch, sb[slot]);
-        if (FINAL && l == 0) Storage<SN>::load4((const SN *)a.fn + nb.c, (uint32_t)ch.k0, sb[slot].b);
+        if (FINAL && l == 0) Storage<SP>::load4((const SP *)a.fn + nb.c, (uint32_t)ch.k0, sb[slot].b);
     };
     if (PF) load_unit(0, 0);
 #pragma unroll
@@ -527,6 +539,14 @@ __global__ __launch_bounds__((64 * waves_per_block<typename Storage<SN>::T, C>()
                 acc[e] = l == 0 ? cl * Lt[e] : acc[e] + cl * Lt[e];
                 if (l == 0) qsum[e] = 0;
             }
+            if constexpr (SIDE) {
+                const T sl = (T)a.scl[l];
+#pragma unroll
+                for (int e = 0; e < 4; ++e) {
+                    pacc[e] = l == 0 ? sl * Lt[e] : pacc[e] + sl * Lt[e];
+                    if (l == 0) psum[e] = 0;
+                }
+            }
             if (l == 0) {
                 // the implicit stages transport f^n first
 #pragma unroll
@@ -539,8 +559,13 @@ __global__ __launch_bounds__((64 * waves_per_block<typename Storage<SN>::T, C>()
                 GaussRow<T> gr;
                 gr.set(gq[q], ch.vy);
                 const T cq = (T)a.cq[q] * dtte;
+                const T sq = SIDE ? (T)a.scq * dtte : (T)0;
 #pragma unroll
-                for (int e = 0; e < 4; ++e) qsum[e] += cq * (gr.hat(gq[q], ch.vx[e]) - cur.c[e]);
+                for (int e = 0; e < 4; ++e) {
+                    const T hm = gr.hat(gq[q], ch.vx[e]) - cur.c[e];
+                    qsum[e] += cq * hm;
+                    if (SIDE) psum[e] += sq * hm;
+                }
             }
             if (l == NL - 1) {
                 T fs[4];
@@ -550,6 +575,13 @@ __global__ __launch_bounds__((64 * waves_per_block<typename Storage<SN>::T, C>()
 #pragma unroll
                 for (int e = 0; e < 4; ++e) lds.v[wave][m][lane][e] = fs[e];
                 if (FINAL && gc.valid) Storage<SN>::store4((SN *)a.fout + nb.c, (uint32_t)ch.k0, fs);
+                if (SIDE && gc.valid) {
+                    // P = f^n - dt sum_j bt_j L(f^(j)) + dt sum_j b_j Q'_j over the stages so far
+                    T pv[4];
+#pragma unroll
+                    for (int e = 0; e < 4; ++e) pv[e] = (base[e] - dt * pacc[e]) + psum[e];
+                    Storage<SP>::store4((SP *)a.sout + nb.c, (uint32_t)ch.k0, pv);
+                }
             }
         }
         if (l == NL - 1 && (m & 3) == 3) macc.fold();
@@ -799,7 +831,7 @@ static inline unsigned grid_for(int nmax, int cells_per_block) {
 #define ESBGK_STATIC_NV(X) X(16, 16, 4) X(32, ESBGK_NV32_L, ESBGK_NV32_C) X(48, 64, 9) X(64, 64, 16)
 #define ESBGK_SHAPES(X) X(0, 16, 4) X(0, 16, 8) X(0, 32, 8) X(0, 64, 9) X(0, 64, 16)
 
-template <class SN, class SS, int NL, int NQ, bool FINAL>
+template <class SN, class SS, int NL, int NQ, bool FINAL, bool SIDE>
 static hipError_t stage_dispatch(const StageArgs &a, int nmax, hipStream_t st) {
     const Shape sh = shape_for(a.g.nv2);
 #define ESBGK_CASE(NN, LL, CC)                                                                                     \
@@ -807,9 +839,9 @@ static hipError_t stage_dispatch(const StageArgs &a, int nmax, hipStream_t st) {
         constexpr int WPB = waves_per_block<typename Storage<SN>::T, CC>();                                         \
         const dim3 grid(grid_for(nmax, WPB * (64 / LL))), block(64 * WPB);                                          \
         if (a.g.recon == 0)                                                                                         \
-            hipLaunchKernelGGL((stage_kernel<SN, SS, NN, LL, CC, NL, NQ, FINAL, 0>), grid, block, 0, st, a);        \
+            hipLaunchKernelGGL((stage_kernel<SN, SS, NN, LL, CC, NL, NQ, FINAL, 0, SIDE>), grid, block, 0, st, a);  \
         else                                                                                                        \
-            hipLaunchKernelGGL((stage_kernel<SN, SS, NN, LL, CC, NL, NQ, FINAL, 1>), grid, block, 0, st, a);        \
+            hipLaunchKernelGGL((stage_kernel<SN, SS, NN, LL, CC, NL, NQ, FINAL, 1, SIDE>), grid, block, 0, st, a);  \
         return hipGetLastError();                                                                                   \
     }
     ESBGK_STATIC_NV(ESBGK_CASE)
@@ -825,10 +857,12 @@ hipError_t launch_stage(const StageArgs &a, int nmax, hipStream_t st) {
         if (a.nl - a.nq + q < 0 || a.fq[q] != a.fl[a.nl - a.nq + q]) return hipErrorInvalidValue;
     if (a.aii > 0.0) {
         if (a.nl < 1 || a.fl[0] != a.fn) return hipErrorInvalidValue;  // implicit stages transport f^n first
-        if (a.nl == 1 && a.nq == 0) return stage_dispatch<SN, SS, 1, 0, false>(a, nmax, st);
-        if (a.nl == 2 && a.nq == 1) return stage_dispatch<SN, SS, 2, 1, false>(a, nmax, st);
+        if (a.nl == 1 && a.nq == 0 && !a.sout) return stage_dispatch<SN, SS, 1, 0, false, false>(a, nmax, st);
+        if (a.nl == 2 && a.nq == 1 && !a.sout) return stage_dispatch<SN, SS, 2, 1, false, false>(a, nmax, st);
+        if (a.nl == 2 && a.nq == 1 && a.sout) return stage_dispatch<SN, SS, 2, 1, false, true>(a, nmax, st);
     } else {
-        if (a.nl == 2 && a.nq == 2) return stage_dispatch<SN, SS, 2, 2, true>(a, nmax, st);
+        // final combination from the partial sum P of the last implicit stage
+        if (a.nl == 1 && a.nq == 1 && !a.sout) return stage_dispatch<SN, SS, 1, 1, true, false>(a, nmax, st);
     }
     return hipErrorInvalidValue;
 }
