@@ -211,10 +211,11 @@ struct TimedLaunch {
     }
 };
 
-int regime_lists(esbgk_ctx *c, const uint8_t *mask_old, hipStream_t st) {
+// Lists of the current mask; `total` (may be null) accumulates the kinetic count.
+int regime_lists(esbgk_ctx *c, const uint8_t *mask_old, hipStream_t st, long long *total = nullptr) {
     const int radius = c->cfg.recon == ESBGK_MINMOD2 ? 2 : 1;
-    HIPCHK(launch_classify(c->mask, mask_old, c->cls, c->cfg.nx, c->cfg.ny, radius, st));
-    HIPCHK(launch_compact(c->cls, c->cfg.nx, c->cfg.ny, c->blockcounts, c->counts, c->kin, c->buf, c->newk, st));
+    HIPCHK(launch_compact(c->mask, mask_old, c->cls, radius, c->cfg.nx, c->cfg.ny, c->blockcounts, c->counts, c->kin,
+                          c->buf, c->newk, total, st));
     return ESBGK_OK;
 }
 
@@ -250,7 +251,6 @@ IndicatorArgs indicator_args(const esbgk_config *cfg) {
     return a;
 }
 
-// One IMEX stage (i = 1, 2) or the final combination (i = 3) on kinetic cells.
 // One IMEX stage (i = 1, 2) or the final combination (i = 3) on kinetic cells.
 // With ARS(2,3,3) the last implicit stage also writes the partial sum
 //   P = f^n - dt sum_{j<3} bt_j L(f^(j)) + dt sum_{j<3} b_j Q'_j
@@ -348,20 +348,20 @@ template <class SN, class SS> int run_step(esbgk_ctx *c, hipStream_t st) {
     int rc;
     // ---- regime update (Algorithm 1: at the start of every step)
     if (c->cfg.indicator == ESBGK_IND_PLAIN) {
-        HIPCHK(launch_prim(c->U[0], c->prim, c->nc, st));
         std::swap(c->mask_old, c->mask);  // the indicator writes the new mask from the previous one
         IndicatorArgs ia = indicator_args(&c->cfg);
-        ia.prim = c->prim; ia.eps = c->eps; ia.l1 = c->l1; ia.mask_old = c->mask_old; ia.mask_new = c->mask;
+        ia.U = c->U[0]; ia.eps = c->eps; ia.l1 = c->l1; ia.mask_old = c->mask_old; ia.mask_new = c->mask;
         HIPCHK(launch_indicator(ia, st));
-        if ((rc = regime_lists(c, c->mask_old, st))) return rc;
+        if ((rc = regime_lists(c, c->mask_old, st, c->kin_total))) return rc;
         // fluid -> kinetic: f = Mhat(U) (eq. Coupling_FluKin); kinetic -> fluid keeps U = moments(f)
         if ((rc = fill_list<SN>(c, c->f[0], c->U[0], c->newk, c->counts + 2, st))) return rc;
     } else if (c->cfg.indicator == ESBGK_IND_LEARNED && c->steps % c->cfg.learned_k == 0) {
         if ((rc = learned_update(c, st))) return rc;
-        if ((rc = regime_lists(c, c->mask_old, st))) return rc;
+        if ((rc = regime_lists(c, c->mask_old, st, c->kin_total))) return rc;
         if ((rc = fill_list<SN>(c, c->f[0], c->U[0], c->newk, c->counts + 2, st))) return rc;
+    } else {
+        HIPCHK(launch_accumulate_count(c->counts, c->kin_total, st));  // the lists are unchanged
     }
-    HIPCHK(launch_accumulate_count(c->counts, c->kin_total, st));
     // ---- stage 1 coupling: buffer cells carry Mhat(U^n)
     if ((rc = fill_list<SN>(c, c->f[0], c->U[0], c->buf, c->counts + 1, st))) return rc;
     // ---- stages 2 and 3

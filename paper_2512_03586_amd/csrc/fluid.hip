@@ -17,14 +17,14 @@ __device__ inline double dminmod(double a, double b) {
 // Physical flux of the compressible Euler system in direction d
 // (eq. Euler_Compact, gamma = 2 so P = E - rho|u|^2/2).
 __device__ inline void euler_flux(const double U[4], int d, double F[4], double *speed) {
-    double rho = U[0], ux = U[1] / rho, uy = U[2] / rho, E = U[3];
-    double P = E - 0.5 * rho * (ux * ux + uy * uy);
-    double un = d == 0 ? ux : uy;
+    const double rho = U[0], irho = 1.0 / rho, ux = U[1] * irho, uy = U[2] * irho, E = U[3];
+    const double P = E - 0.5 * rho * (ux * ux + uy * uy);
+    const double un = d == 0 ? ux : uy;
     F[0] = rho * un;
     F[1] = U[1] * un + (d == 0 ? P : 0.0);
     F[2] = U[2] * un + (d == 1 ? P : 0.0);
     F[3] = un * (E + P);
-    *speed = fabs(un) + sqrt(2.0 * P / rho);
+    *speed = fabs(un) + sqrt(2.0 * P * irho);
 }
 
 // Rusanov flux (Sec. 3.2, Lax-Friedrichs type) at the face between stencil
@@ -52,11 +52,11 @@ __device__ inline void euler_face_vals(const double st[4][4], int d, int recon, 
 }
 
 // U^(i) = U^n - dt sum_j c_j Phi(U^(j)) on fluid cells (eqs. RKEuler, RKEuler_2).
-// One 16 x 16 tile of cells per block: each U^(j) tile with its 2-cell
-// periodic halo is staged in LDS, every face flux of the tile is computed once
-// (17 x 16 faces per direction), and each cell takes the difference of its two
-// faces per direction.
-constexpr int ET = 16, EH = 2, EW = ET + 2 * EH;
+// One 8 x 8 tile of cells per one-wavefront block: each U^(j) tile with its
+// 2-cell periodic halo is staged in LDS, every face flux of the tile is
+// computed once (9 x 8 faces per direction), and each cell takes the
+// difference of its two faces per direction.
+constexpr int ET = 8, EH = 2, EW = ET + 2 * EH;
 
 __global__ __launch_bounds__(ET * ET) void euler_stage_kernel(EulerArgs a) {
     __shared__ double u[4][EW][EW];
@@ -114,10 +114,10 @@ __global__ __launch_bounds__(ET * ET) void euler_stage_kernel(EulerArgs a) {
             for (int q = 0; q < 4; ++q) fy[q][f][cidx] = F[q];
         }
         __syncthreads();
-        const double c = a.dt * a.cj[jj];
+        const double c = a.dt * a.cj[jj], idx = 1.0 / a.dx, idy = 1.0 / a.dy;
 #pragma unroll
         for (int q = 0; q < 4; ++q)
-            s[q] -= c * ((fx[q][ty][tx + 1] - fx[q][ty][tx]) / a.dx + (fy[q][ty + 1][tx] - fy[q][ty][tx]) / a.dy);
+            s[q] -= c * ((fx[q][ty][tx + 1] - fx[q][ty][tx]) * idx + (fy[q][ty + 1][tx] - fy[q][ty][tx]) * idy);
         __syncthreads();
     }
     if (fluid) {
@@ -186,14 +186,27 @@ __device__ inline uint8_t indicator_cell(const IndicatorArgs &a, int cell, doubl
     const int i = cell % nx, j = cell / nx;
     const size_t ce = (size_t)j * nx + wrapc(i + 1, nx), cw = (size_t)j * nx + wrapc(i - 1, nx);
     const size_t cn = (size_t)wrapc(j + 1, ny) * nx + i, cs = (size_t)wrapc(j - 1, ny) * nx + i;
-    const double *ux = a.prim + n, *uy = a.prim + 2 * n, *T = a.prim + 3 * n;
+    // primitives of the 5-point stencil: read, or formed from U with prim_of
+    double pux[5], puy[5], pT[5];  // order: centre, e, w, n, s
+    const size_t st[5] = {(size_t)cell, ce, cw, cn, cs};
+#pragma unroll
+    for (int q = 0; q < 5; ++q) {
+        if (a.U) {
+            double r;
+            prim_of(a.U[st[q]], a.U[n + st[q]], a.U[2 * n + st[q]], a.U[3 * n + st[q]], &r, &pux[q], &puy[q], &pT[q]);
+        } else {
+            pux[q] = a.prim[n + st[q]];
+            puy[q] = a.prim[2 * n + st[q]];
+            pT[q] = a.prim[3 * n + st[q]];
+        }
+    }
     const double twodx = a.twodx, twody = a.twody;
-    const double uxx = (ux[ce] - ux[cw]) / twodx;
-    const double uxy = (ux[cn] - ux[cs]) / twody;
-    const double uyx = (uy[ce] - uy[cw]) / twodx;
-    const double uyy = (uy[cn] - uy[cs]) / twody;
-    const double Tx = (T[ce] - T[cw]) / twodx;
-    const double Ty = (T[cn] - T[cs]) / twody;
+    const double uxx = (pux[1] - pux[2]) / twodx;
+    const double uxy = (pux[3] - pux[4]) / twody;
+    const double uyx = (puy[1] - puy[2]) / twodx;
+    const double uyy = (puy[3] - puy[4]) / twody;
+    const double Tx = (pT[1] - pT[2]) / twodx;
+    const double Ty = (pT[3] - pT[4]) / twody;
     const double div = uxx + uyy;
     const double Dxx = (uxx + uxx) - a.cD * div;
     const double Dxy = uxy + uyx;
@@ -201,7 +214,7 @@ __device__ inline uint8_t indicator_cell(const IndicatorArgs &a, int cell, doubl
     const double e = a.eps[cell];
     const double cv = e / (a.tau * a.omb);
     const double ke = a.ck * e;
-    const double kt2 = a.cS * ((ke * ke) / ((a.tau * a.tau) * T[cell]));
+    const double kt2 = a.cS * ((ke * ke) / ((a.tau * a.tau) * pT[0]));
     const double a11 = -(cv * Dxx) - kt2 * (Tx * Tx);
     const double a12 = -(cv * Dxy) - kt2 * (Tx * Ty);
     const double a22 = -(cv * Dyy) - kt2 * (Ty * Ty);
@@ -229,26 +242,6 @@ __global__ void indicator_kernel(IndicatorArgs a) {
 
 // class bits: 1 kinetic, 2 buffer (fluid cell inside a kinetic stencil),
 // 4 newly kinetic (needs f = Mhat(U)).
-__global__ void classify_kernel(const uint8_t *mask, const uint8_t *mask_old, uint8_t *cls, int nx,
-                                int ny, int radius) {
-    const int c = blockIdx.x * blockDim.x + threadIdx.x;
-    if (c >= nx * ny) return;
-    const int i = c % nx, j = c / nx;
-    uint8_t k = mask[c];
-    uint8_t out = 0;
-    if (k) {
-        out = 1;
-        if (mask_old && !mask_old[c]) out |= 4;
-    } else {
-        bool near = false;
-        for (int d = 1; d <= radius; ++d) {
-            near = near || mask[(size_t)j * nx + wrapc(i - d, nx)] || mask[(size_t)j * nx + wrapc(i + d, nx)] ||
-                   mask[(size_t)wrapc(j - d, ny) * nx + i] || mask[(size_t)wrapc(j + d, ny) * nx + i];
-        }
-        if (near) out = 2;
-    }
-    cls[c] = out;
-}
 
 // Position -> cell in the processing order: 8x8 cell tiles, row-major inside
 // a tile, tiles row-major; -1 for positions of a padded edge tile.
@@ -259,95 +252,100 @@ __device__ inline int pos_to_cell(int pos, int nx, int ny) {
     return (i < nx && j < ny) ? j * nx + i : -1;
 }
 
-constexpr int kScanBlock = 1024;  // positions per block (256 threads x 4)
+constexpr int kScanBlock = 1024;  // positions per block, one per thread
 
-__global__ __launch_bounds__(256) void scan_count_kernel(const uint8_t *cls, int nx, int ny, int npos,
-                                                         int *blockcounts, int nblocks) {
-    __shared__ int red[3][256];
-    const int t = threadIdx.x;
-    int c3[3] = {0, 0, 0};
-    for (int e = 0; e < 4; ++e) {
-        int pos = blockIdx.x * kScanBlock + t * 4 + e;
-        if (pos < npos) {
-            int cell = pos_to_cell(pos, nx, ny);
-            if (cell >= 0) {
-                uint8_t k = cls[cell];
-                c3[0] += (k & 1) != 0;
-                c3[1] += (k & 2) != 0;
-                c3[2] += (k & 4) != 0;
-            }
+__device__ inline uint8_t class_of(const uint8_t *mask, const uint8_t *mask_old, int c, int nx, int ny, int radius) {
+    const int i = c % nx, j = c / nx;
+    uint8_t out = 0;
+    if (mask[c]) {
+        out = 1;
+        if (mask_old && !mask_old[c]) out |= 4;
+    } else {
+        bool near = false;
+        for (int d = 1; d <= radius; ++d) {
+            near = near || mask[(size_t)j * nx + wrapc(i - d, nx)] || mask[(size_t)j * nx + wrapc(i + d, nx)] ||
+                   mask[(size_t)wrapc(j - d, ny) * nx + i] || mask[(size_t)wrapc(j + d, ny) * nx + i];
         }
+        if (near) out = 2;
     }
-    for (int q = 0; q < 3; ++q) red[q][t] = c3[q];
-    __syncthreads();
-    for (int s = 128; s > 0; s >>= 1) {
-        if (t < s)
-            for (int q = 0; q < 3; ++q) red[q][t] += red[q][t + s];
-        __syncthreads();
-    }
-    if (t == 0)
-        for (int q = 0; q < 3; ++q) blockcounts[q * nblocks + blockIdx.x] = red[q][0];
+    return out;
 }
 
-// Single block: exclusive scan of the per-block counts (in place), totals to counts[0..2].
-__global__ __launch_bounds__(1024) void scan_blocks_kernel(int *blockcounts, int nblocks, int *counts) {
-    __shared__ int buf[1024];
+// Classification of every cell (written to cls) and the per-block counts of
+// the three classes in processing order.
+__global__ __launch_bounds__(kScanBlock) void classify_count_kernel(const uint8_t *mask, const uint8_t *mask_old,
+                                                                    uint8_t *cls, int radius, int nx, int ny,
+                                                                    int npos, int *blockcounts, int nblocks) {
     const int t = threadIdx.x;
-    for (int q = 0; q < 3; ++q) {
-        int *bc = blockcounts + q * nblocks;
-        int carry = 0;
-        for (int base = 0; base < nblocks; base += 1024) {
-            int v = (base + t < nblocks) ? bc[base + t] : 0;
-            buf[t] = v;
-            __syncthreads();
-            for (int off = 1; off < 1024; off <<= 1) {
-                int add = t >= off ? buf[t - off] : 0;
-                __syncthreads();
-                buf[t] += add;
-                __syncthreads();
-            }
-            if (base + t < nblocks) bc[base + t] = carry + buf[t] - v;
-            int tot = buf[1023];
-            __syncthreads();
-            carry += tot;
+    const int pos = blockIdx.x * kScanBlock + t;
+    uint8_t k = 0;
+    if (pos < npos) {
+        const int cell = pos_to_cell(pos, nx, ny);
+        if (cell >= 0) {
+            k = class_of(mask, mask_old, cell, nx, ny, radius);
+            cls[cell] = k;
         }
-        if (t == 0) counts[q] = carry;
-        __syncthreads();
+    }
+    const int n1 = __syncthreads_count((k & 1) != 0);
+    const int n2 = __syncthreads_count((k & 2) != 0);
+    const int n4 = __syncthreads_count((k & 4) != 0);
+    if (t == 0) {
+        blockcounts[blockIdx.x] = n1;
+        blockcounts[nblocks + blockIdx.x] = n2;
+        blockcounts[2 * nblocks + blockIdx.x] = n4;
     }
 }
 
-__global__ __launch_bounds__(256) void scan_scatter_kernel(const uint8_t *cls, int nx, int ny, int npos,
-                                                           const int *blockoff, int nblocks, int *kin,
-                                                           int *buf, int *newk) {
-    __shared__ int sc[3][256];
+// Scatter of the three lists in processing order.  Each block first sums
+// the counts of the blocks before it (a fixed-order reduction, so the lists
+// are deterministic); the last block writes the totals to counts[0..2] and
+// adds the kinetic count to *total (when given).
+__global__ __launch_bounds__(kScanBlock) void scan_scatter_kernel(const uint8_t *cls, int nx, int ny, int npos,
+                                                                  const int *blockcounts, int nblocks, int *kin,
+                                                                  int *buf, int *newk, int *counts, long long *total) {
+    __shared__ int sc[3][kScanBlock];
+    __shared__ int boff[3];
     const int t = threadIdx.x;
-    int cells[4];
-    uint8_t ks[4];
-    int loc[3] = {0, 0, 0};
-    for (int e = 0; e < 4; ++e) {
-        int pos = blockIdx.x * kScanBlock + t * 4 + e;
-        int cell = pos < npos ? pos_to_cell(pos, nx, ny) : -1;
-        cells[e] = cell;
-        ks[e] = cell >= 0 ? cls[cell] : 0;
-        loc[0] += (ks[e] & 1) != 0;
-        loc[1] += (ks[e] & 2) != 0;
-        loc[2] += (ks[e] & 4) != 0;
+    {
+        int part[3] = {0, 0, 0};
+        for (int b = t; b < (int)blockIdx.x; b += kScanBlock)
+#pragma unroll
+            for (int q = 0; q < 3; ++q) part[q] += blockcounts[q * nblocks + b];
+#pragma unroll
+        for (int q = 0; q < 3; ++q) sc[q][t] = part[q];
+        __syncthreads();
+        for (int s2 = kScanBlock / 2; s2 > 0; s2 >>= 1) {
+            if (t < s2)
+#pragma unroll
+                for (int q = 0; q < 3; ++q) sc[q][t] += sc[q][t + s2];
+            __syncthreads();
+        }
+        if (t < 3) boff[t] = sc[t][0];
+        __syncthreads();
     }
+    const int pos = blockIdx.x * kScanBlock + t;
+    const int cell = pos < npos ? pos_to_cell(pos, nx, ny) : -1;
+    const uint8_t k = cell >= 0 ? cls[cell] : 0;
+    int loc[3] = {(k & 1) != 0, (k & 2) != 0, (k & 4) != 0};
+    // inclusive scan of the block's flags (Hillis-Steele in LDS)
+#pragma unroll
     for (int q = 0; q < 3; ++q) sc[q][t] = loc[q];
     __syncthreads();
-    for (int off = 1; off < 256; off <<= 1) {
+    for (int off = 1; off < kScanBlock; off <<= 1) {
         int add[3];
+#pragma unroll
         for (int q = 0; q < 3; ++q) add[q] = t >= off ? sc[q][t - off] : 0;
         __syncthreads();
+#pragma unroll
         for (int q = 0; q < 3; ++q) sc[q][t] += add[q];
         __syncthreads();
     }
-    int o[3];
-    for (int q = 0; q < 3; ++q) o[q] = blockoff[q * nblocks + blockIdx.x] + sc[q][t] - loc[q];
-    for (int e = 0; e < 4; ++e) {
-        if (ks[e] & 1) kin[o[0]++] = cells[e];
-        if (ks[e] & 2) buf[o[1]++] = cells[e];
-        if (ks[e] & 4) newk[o[2]++] = cells[e];
+    if (k & 1) kin[boff[0] + sc[0][t] - 1] = cell;
+    if (k & 2) buf[boff[1] + sc[1][t] - 1] = cell;
+    if (k & 4) newk[boff[2] + sc[2][t] - 1] = cell;
+    if ((int)blockIdx.x == nblocks - 1 && t == kScanBlock - 1) {
+        for (int q = 0; q < 3; ++q) counts[q] = boff[q] + sc[q][t];
+        if (total) *total += boff[0] + sc[0][t];
     }
 }
 
@@ -464,23 +462,17 @@ hipError_t launch_indicator(const IndicatorArgs &a, hipStream_t st) {
     return hipGetLastError();
 }
 
-hipError_t launch_classify(const uint8_t *mask, const uint8_t *mask_old, uint8_t *cls, int nx, int ny,
-                           int radius, hipStream_t st) {
-    hipLaunchKernelGGL(classify_kernel, dim3(cells_grid(nx * ny)), dim3(256), 0, st, mask, mask_old, cls,
-                       nx, ny, radius);
-    return hipGetLastError();
-}
-
 int scan_positions(int nx, int ny) { return ((nx + 7) / 8) * ((ny + 7) / 8) * 64; }
 int scan_nblocks(int nx, int ny) { return (scan_positions(nx, ny) + kScanBlock - 1) / kScanBlock; }
 
-hipError_t launch_compact(const uint8_t *cls, int nx, int ny, int *blockcounts, int *counts, int *kin,
-                          int *buf, int *newk, hipStream_t st) {
+hipError_t launch_compact(const uint8_t *mask, const uint8_t *mask_old, uint8_t *cls, int radius, int nx, int ny,
+                          int *blockcounts, int *counts, int *kin, int *buf, int *newk, long long *total,
+                          hipStream_t st) {
     const int npos = scan_positions(nx, ny), nb = scan_nblocks(nx, ny);
-    hipLaunchKernelGGL(scan_count_kernel, dim3(nb), dim3(256), 0, st, cls, nx, ny, npos, blockcounts, nb);
-    hipLaunchKernelGGL(scan_blocks_kernel, dim3(1), dim3(1024), 0, st, blockcounts, nb, counts);
-    hipLaunchKernelGGL(scan_scatter_kernel, dim3(nb), dim3(256), 0, st, cls, nx, ny, npos, blockcounts, nb,
-                       kin, buf, newk);
+    hipLaunchKernelGGL(classify_count_kernel, dim3(nb), dim3(kScanBlock), 0, st, mask, mask_old, cls, radius, nx, ny,
+                       npos, blockcounts, nb);
+    hipLaunchKernelGGL(scan_scatter_kernel, dim3(nb), dim3(kScanBlock), 0, st, cls, nx, ny, npos, blockcounts, nb, kin,
+                       buf, newk, counts, total);
     return hipGetLastError();
 }
 

@@ -69,7 +69,8 @@ struct IndicatorArgs {
     double tau, omb;     // omb = 1 - beta
     double cD, ck, cS;
     double eta, delta;
-    const double *prim;  // SoA [4][nc] = (rho, ux, uy, T)
+    const double *prim;  // SoA [4][nc] = (rho, ux, uy, T); read when U is null
+    const double *U;     // SoA [4][nc] conserved variables: primitives formed in the kernel
     const double *eps;
     const double *l1;
     const uint8_t *mask_old;
@@ -89,10 +90,12 @@ hipError_t launch_conserved(const double *rho, const double *ux, const double *u
                             const double *eps, double *U, double *eps_out, int nc, int *bad,
                             hipStream_t st);
 hipError_t launch_indicator(const IndicatorArgs &a, hipStream_t st);
-hipError_t launch_classify(const uint8_t *mask, const uint8_t *mask_old, uint8_t *cls, int nx, int ny,
-                           int radius, hipStream_t st);
-hipError_t launch_compact(const uint8_t *cls, int nx, int ny, int *blockcounts, int *counts, int *kin,
-                          int *buf, int *newk, hipStream_t st);
+// Classification (1 kinetic, 2 buffer within `radius` cells of a kinetic
+// cell, 4 newly kinetic) and the deterministic compaction of the three lists;
+// adds the kinetic count to *total when total is given.
+hipError_t launch_compact(const uint8_t *mask, const uint8_t *mask_old, uint8_t *cls, int radius, int nx, int ny,
+                          int *blockcounts, int *counts, int *kin, int *buf, int *newk, long long *total,
+                          hipStream_t st);
 hipError_t launch_get_prim(const double *U, double *rho, double *ux, double *uy, double *T, int nc,
                            hipStream_t st);
 hipError_t launch_accumulate_count(const int *counts, long long *total, hipStream_t st);

@@ -202,11 +202,13 @@ template <int L, int WPB = 4> __device__ inline GroupCell group_cell(const int *
     return gc;
 }
 
-// Chunk m of sub-lane s.  NV > 0 is the velocity grid size known at compile
-// time: when L is a multiple of NV/4 every lane keeps the same x-velocities in
-// all its chunks and each chunk's y-row (hence its upwind direction) is a
-// compile-time function of m, so neighbour selection and addressing fold into
-// constants.  NV = 0 reads the size from g.
+// Chunk m of sub-lane s: chunk c = s + L m covers nodes 4c .. 4c+3 in
+// row-major order (whole 128-byte rows per wave-wide load).  NV > 0 is the
+// velocity grid size known at compile time: when L is a multiple of NV/4
+// every lane keeps the same x-velocities in all its chunks and each chunk's
+// y-row (hence its upwind direction) is a compile-time function of m, so
+// neighbour selection and addressing fold into constants.  NV = 0 reads the
+// size from g.
 template <class T, int L, int NV>
 __device__ inline Chunk<T> chunk_of(int s, int m, const Geom &g) {
     Chunk<T> ch;
@@ -496,97 +498,103 @@ __global__ __launch_bounds__((64 * waves_per_block<typename Storage<SN>::T, C>()
 #pragma unroll
     for (int q = 0; q < NQ; ++q) gq[q].load(a.pq[q] + (size_t)cell * GP_N);
 
-    // ---- explicit part of the stage, moments on the fly.  Work unit u =
-    // (chunk m = u / NL, transported array l = u % NL); with prefetching the
-    // loads of unit u + 1 are in flight while unit u is computed.  The source
-    // arrays of the implicit terms are the last NQ transported arrays (the
-    // launcher checks this), so their values are the stencil centres.
+    // ---- explicit part of the stage, moments on the fly
     MomentAcc<T> macc;
     constexpr int NU = C * NL;
     constexpr bool PF = ESBGK_PREFETCH != 0;
     constexpr int NB = PF ? 2 : 1;
-    Stencil<T> sb[NB];
     T base[4], acc[4], qsum[4];  // base: f^n at the cell (final combination: the partial sum P)
     T pacc[4], psum[4];          // side output P of the last implicit stage
-    auto load_unit = [&](int u, int slot) {
-        const int m = u / NL, l = u % NL;
-        const Chunk<T> ch = chunk_of<T, L, NV>(s, m, g);
-        if (!ch.active) return;
-        if (!FINAL && l == 0)
-            load_stencil<SN, RECON>((const SN *)a.fl[0], nb, ch, sb[slot]);
-        else
-            load_stencil<SS, RECON>((const SS *)a.fl[l], nb, ch, sb[slot]);
-        if (FINAL && l == 0) Storage<SP>::load4((const SP *)a.fn + nb.c, (uint32_t)ch.k0, sb[slot].b);
-    };
-    if (PF) load_unit(0, 0);
+    // Per-unit work once its transport Lt and centre values cc are known.
+    auto unit_body = [&](int m, int l, const Chunk<T> &ch, const T Lt[4], const T cc[4]) {
+        const T cl = (T)a.cl[l];
 #pragma unroll
-    for (int u = 0; u < NU; ++u) {
-        const int m = u / NL, l = u % NL;
-        const int slot = PF ? (u & 1) : 0;
-        const Chunk<T> ch = chunk_of<T, L, NV>(s, m, g);
-        if (PF) {
-            if (u + 1 < NU) load_unit(u + 1, (u + 1) & 1);
-        } else {
-            load_unit(u, 0);
+        for (int e = 0; e < 4; ++e) {
+            acc[e] = l == 0 ? cl * Lt[e] : acc[e] + cl * Lt[e];
+            if (l == 0) qsum[e] = 0;
         }
-        const Stencil<T> &cur = sb[slot];
-        if (ch.active) {
-            T Lt[4];
-            transport_of<T, RECON>(cur, ch, idx, idy, Lt);
-            const T cl = (T)a.cl[l];
+        if constexpr (SIDE) {
+            const T sl = (T)a.scl[l];
 #pragma unroll
             for (int e = 0; e < 4; ++e) {
-                acc[e] = l == 0 ? cl * Lt[e] : acc[e] + cl * Lt[e];
-                if (l == 0) qsum[e] = 0;
-            }
-            if constexpr (SIDE) {
-                const T sl = (T)a.scl[l];
-#pragma unroll
-                for (int e = 0; e < 4; ++e) {
-                    pacc[e] = l == 0 ? sl * Lt[e] : pacc[e] + sl * Lt[e];
-                    if (l == 0) psum[e] = 0;
-                }
-            }
-            if (l == 0) {
-                // the implicit stages transport f^n first
-#pragma unroll
-                for (int e = 0; e < 4; ++e) base[e] = FINAL ? cur.b[e] : cur.c[e];
-            }
-            // implicit term of the stage whose state this unit transports
-            constexpr int Q0 = NL - NQ;
-            if (l >= Q0) {
-                const int q = l - Q0 < NQ ? l - Q0 : 0;
-                GaussRow<T> gr;
-                gr.set(gq[q], ch.vy);
-                const T cq = (T)a.cq[q] * dtte;
-                const T sq = SIDE ? (T)a.scq * dtte : (T)0;
-#pragma unroll
-                for (int e = 0; e < 4; ++e) {
-                    const T hm = gr.hat(gq[q], ch.vx[e]) - cur.c[e];
-                    qsum[e] += cq * hm;
-                    if (SIDE) psum[e] += sq * hm;
-                }
-            }
-            if (l == NL - 1) {
-                T fs[4];
-#pragma unroll
-                for (int e = 0; e < 4; ++e) fs[e] = (base[e] - dt * acc[e]) + qsum[e];
-                macc.add(ch, fs);
-#pragma unroll
-                for (int e = 0; e < 4; ++e) lds.v[wave][m][lane][e] = fs[e];
-                if (FINAL && gc.valid) Storage<SN>::store4((SN *)a.fout + nb.c, (uint32_t)ch.k0, fs);
-                if (SIDE && gc.valid) {
-                    // P = f^n - dt sum_j bt_j L(f^(j)) + dt sum_j b_j Q'_j over the stages so far
-                    T pv[4];
-#pragma unroll
-                    for (int e = 0; e < 4; ++e) pv[e] = (base[e] - dt * pacc[e]) + psum[e];
-                    Storage<SP>::store4((SP *)a.sout + nb.c, (uint32_t)ch.k0, pv);
-                }
+                pacc[e] = l == 0 ? sl * Lt[e] : pacc[e] + sl * Lt[e];
+                if (l == 0) psum[e] = 0;
             }
         }
-        if (l == NL - 1 && (m & 3) == 3) macc.fold();
-        // bounded register use: at most two units' loads live at a time
-        __builtin_amdgcn_sched_barrier(0);
+        // implicit term of the stage whose state this unit transports
+        constexpr int Q0 = NL - NQ;
+        if (l >= Q0) {
+            const int q = l - Q0 < NQ ? l - Q0 : 0;
+            GaussRow<T> gr;
+            gr.set(gq[q], ch.vy);
+            const T cq = (T)a.cq[q] * dtte;
+            const T sq = SIDE ? (T)a.scq * dtte : (T)0;
+#pragma unroll
+            for (int e = 0; e < 4; ++e) {
+                const T hm = gr.hat(gq[q], ch.vx[e]) - cc[e];
+                qsum[e] += cq * hm;
+                if (SIDE) psum[e] += sq * hm;
+            }
+        }
+        if (l == NL - 1) {
+            T fs[4];
+#pragma unroll
+            for (int e = 0; e < 4; ++e) fs[e] = (base[e] - dt * acc[e]) + qsum[e];
+            macc.add(ch, fs);
+#pragma unroll
+            for (int e = 0; e < 4; ++e) lds.v[wave][m][lane][e] = fs[e];
+            if (FINAL && gc.valid) Storage<SN>::store4((SN *)a.fout + nb.c, (uint32_t)ch.k0, fs);
+            if (SIDE && gc.valid) {
+                // P = f^n - dt sum_j bt_j L(f^(j)) + dt sum_j b_j Q'_j over the stages so far
+                T pv[4];
+#pragma unroll
+                for (int e = 0; e < 4; ++e) pv[e] = (base[e] - dt * pacc[e]) + psum[e];
+                Storage<SP>::store4((SP *)a.sout + nb.c, (uint32_t)ch.k0, pv);
+            }
+        }
+    };
+    // Work unit u = (chunk m = u / NL, transported array l = u % NL); with
+    // prefetching the loads of the next (half) unit are in flight while the
+    // current one is computed.  The source arrays of the implicit terms are
+    // the last NQ transported arrays (the launcher checks this), so their
+    // values are the stencil centres.
+    {
+        Stencil<T> sb[NB];
+        auto load_unit = [&](int u, int slot) {
+            const int m = u / NL, l = u % NL;
+            const Chunk<T> ch = chunk_of<T, L, NV>(s, m, g);
+            if (!ch.active) return;
+            if (!FINAL && l == 0)
+                load_stencil<SN, RECON>((const SN *)a.fl[0], nb, ch, sb[slot]);
+            else
+                load_stencil<SS, RECON>((const SS *)a.fl[l], nb, ch, sb[slot]);
+            if (FINAL && l == 0) Storage<SP>::load4((const SP *)a.fn + nb.c, (uint32_t)ch.k0, sb[slot].b);
+        };
+        if (PF) load_unit(0, 0);
+#pragma unroll
+        for (int u = 0; u < NU; ++u) {
+            const int m = u / NL, l = u % NL;
+            const int slot = PF ? (u & 1) : 0;
+            const Chunk<T> ch = chunk_of<T, L, NV>(s, m, g);
+            if (PF) {
+                if (u + 1 < NU) load_unit(u + 1, (u + 1) & 1);
+            } else {
+                load_unit(u, 0);
+            }
+            const Stencil<T> &cur = sb[slot];
+            if (ch.active) {
+                if (l == 0) {
+#pragma unroll
+                    for (int e = 0; e < 4; ++e) base[e] = FINAL ? cur.b[e] : cur.c[e];  // stages transport f^n first
+                }
+                T Lt[4];
+                transport_of<T, RECON>(cur, ch, idx, idy, Lt);
+                unit_body(m, l, ch, Lt, cur.c);
+            }
+            if (l == NL - 1 && (m & 3) == 3) macc.fold();
+            // bounded register use: at most two units' loads live at a time
+            __builtin_amdgcn_sched_barrier(0);
+        }
     }
 
     // ---- moments of f*
