@@ -82,6 +82,12 @@ def parse():
     ap.add_argument("--warmup", type=int, default=10)
     ap.add_argument("--precision", default="fp32", choices=["fp32", "bf16", "fp64", "mixed"])
     ap.add_argument("--workload", default="riemann4", choices=sorted(WORKLOADS))
+    ap.add_argument("--indicator", default="plain", choices=["plain", "learned", "dilated"],
+                    help="plain: the criterion every step; learned: the trained network between plain checks "
+                         "every --learned-k steps (trained first, untimed, on other seeds of the generator); "
+                         "dilated: the plain check every K steps with its mask dilated")
+    ap.add_argument("--learned-k", type=int, default=10)
+    ap.add_argument("--train-seeds", type=int, default=8)
     ap.add_argument("--no-cpu-baseline", action="store_true")
     ap.add_argument("--cpu-steps", type=int, default=16)
     ap.add_argument("--calibrate-copy", type=int, default=0, metavar="MIB",
@@ -143,9 +149,27 @@ def main():
     es = ELEM[args.precision]
     nx, nv, vmax = wl["nx"], wl["nv"], wl["vmax"]
     d = getattr(inputs, wl["gen"])(nx=nx, ny=nx, nv=nv, vmax=vmax, **wl["kw"])
-    cfg = E.make_config(nx, nx, nv, vmax, precision=prec, indicator=E.IND_PLAIN, scheme=E.ARS233,
-                        recon=E.MINMOD2, eta=1e-2, delta=1e-3)
+    learned_info = None
+    ind = {"plain": E.IND_PLAIN, "learned": E.IND_LEARNED, "dilated": E.IND_LEARNED}[args.indicator]
+    cfg = E.make_config(nx, nx, nv, vmax, precision=prec, indicator=ind, scheme=E.ARS233,
+                        recon=E.MINMOD2, eta=1e-2, delta=1e-3, learned_k=args.learned_k)
     eng = E.Engine(cfg)
+    if args.indicator != "plain":
+        from paper_2512_03586_amd import learned as LR
+        K = args.learned_k
+        if args.indicator == "learned":
+            t0 = time.perf_counter()
+            kw = dict(nx=nx, nv=nv, vmax=vmax, steps=wl["steps"] // 2, K=K, precision=prec)
+            train = LR.collect(range(1, 1 + args.train_seeds), **kw)
+            val = LR.collect(range(100, 102), **kw)
+            net, res = LR.train(train, val, iters=1500, batch=16384, lr=3e-3, w_pos=4.0, miss=2e-3)
+            torch.cuda.synchronize()
+            eng.set_learned(net, res.threshold)
+            learned_info = {"K": K, "train_seeds": args.train_seeds, "train_seconds_incl_data": round(time.perf_counter() - t0, 2),
+                            "threshold": res.threshold, "val_recall": res.val_recall}
+        else:
+            eng.set_learned(None, 0.0, LR.dilation_radius(K))
+            learned_info = {"K": K, "dilation": LR.dilation_radius(K)}
     dev = {k: torch.as_tensor(d[k]).cuda() for k in ("rho", "ux", "uy", "T", "eps")}
 
     def reset():
@@ -193,7 +217,10 @@ def main():
                   "mixed": "f32-state/bf16-stages/f32"}[args.precision],
         "data": "synthetic",
         "config": {"workload": f"{wl['gen']} {nx}x{nx} cells x {nv}x{nv} velocities on [-{vmax:g},{vmax:g}]^2, "
-                               f"ARS(2,3,3), minmod, regime update every step, {args.steps} steps from t=0",
+                               f"ARS(2,3,3), minmod, "
+                               + ("regime update every step" if args.indicator == "plain" else
+                                  f"{args.indicator} indicator, plain check every {args.learned_k} steps")
+                               + f", {args.steps} steps from t=0",
                    "nx": nx, "ny": nx, "nv": nv, "precision": args.precision,
                    "kinetic_cells_per_step": round(kin_avg, 1),
                    "kernel_ms_per_launch": breakdown},
@@ -204,6 +231,11 @@ def main():
     }
     if stats.error_flags:
         out["error_flags"] = stats.error_flags
+    if learned_info is not None:
+        checks, missed, extra, plain_kin = eng.learned_stats()
+        learned_info.update(checks=checks, missed_cell_rate=missed / max(checks * nx * nx, 1),
+                            extra_cell_rate=extra / max(checks * nx * nx, 1))
+        out["config"]["indicator"] = learned_info
     if not args.no_cpu_baseline:
         out["cpu_baseline"] = cpu_baseline(wl, args.cpu_steps)
     print(json.dumps(out))
