@@ -52,75 +52,81 @@ __device__ inline void euler_face_vals(const double st[4][4], int d, int recon, 
 }
 
 // U^(i) = U^n - dt sum_j c_j Phi(U^(j)) on fluid cells (eqs. RKEuler, RKEuler_2).
-// One 8 x 8 tile of cells per one-wavefront block: each U^(j) tile with its
-// 2-cell periodic halo is staged in LDS, every face flux of the tile is
-// computed once (9 x 8 faces per direction), and each cell takes the
-// difference of its two faces per direction.
-constexpr int ET = 8, EH = 2, EW = ET + 2 * EH;
+// One 8 x 8 tile of cells per 4-wavefront block: the U^(j) tiles with their
+// 2-cell periodic halo are staged in LDS, every face flux of the tile is
+// computed once (9 x 8 faces per direction and stage array, one thread per
+// face, so the divide / square-root chains of many faces interleave), and
+// each cell takes the difference of its two faces per direction.
+constexpr int ET = 8, EH = 2, EW = ET + 2 * EH, ENT = 256, ENJ = 3;
+constexpr int EFACES = ET * (ET + 1);  // faces per direction
 
-__global__ __launch_bounds__(ET * ET) void euler_stage_kernel(EulerArgs a) {
-    __shared__ double u[4][EW][EW];
-    __shared__ double fx[4][ET][ET + 1];
-    __shared__ double fy[4][ET + 1][ET];
-    const int tx = (int)threadIdx.x % ET, ty = (int)threadIdx.x / ET, tid = (int)threadIdx.x;
+__global__ __launch_bounds__(ENT) void euler_stage_kernel(EulerArgs a) {
+    __shared__ double u[ENJ][4][EW][EW];
+    __shared__ double fx[ENJ][4][ET][ET + 1];
+    __shared__ double fy[ENJ][4][ET + 1][ET];
+    const int tid = (int)threadIdx.x;
     const int i0 = (int)blockIdx.x * ET, j0 = (int)blockIdx.y * ET;
-    const int nx = a.nx, ny = a.ny;
+    const int nx = a.nx, ny = a.ny, nj = a.nj;
     const size_t nc = (size_t)a.nc;
+    // cell of threads 0..63
+    const int tx = tid % ET, ty = tid / ET;
     const int i = i0 + tx, j = j0 + ty;
-    const bool own = i < nx && j < ny;
+    const bool own = tid < ET * ET && i < nx && j < ny;
     const size_t cell = own ? (size_t)j * nx + i : 0;
     const bool fluid = own && !a.mask[cell];
     if (!__syncthreads_or(fluid)) return;  // whole tile kinetic (or outside)
-    double s[4] = {0, 0, 0, 0};
-    if (fluid) {
-#pragma unroll
-        for (int q = 0; q < 4; ++q) s[q] = a.Un[q * nc + cell];
-    }
-    for (int jj = 0; jj < a.nj; ++jj) {
+    for (int t = tid; t < nj * EW * EW; t += ENT) {
+        const int jj = t / (EW * EW), r = t % (EW * EW);
+        const int li = r % EW, lj = r / EW;
+        const int gi = wrapc(i0 + li - EH, nx), gj = wrapc(j0 + lj - EH, ny);
+        const size_t c = (size_t)gj * nx + gi;
         const double *U = a.Uj[jj];
-        for (int t = tid; t < EW * EW; t += ET * ET) {
-            const int li = t % EW, lj = t / EW;
-            const int gi = wrapc(i0 + li - EH, nx), gj = wrapc(j0 + lj - EH, ny);
-            const size_t c = (size_t)gj * nx + gi;
 #pragma unroll
-            for (int q = 0; q < 4; ++q) u[q][lj][li] = U[q * nc + c];
-        }
-        __syncthreads();
-        // x-face f (0..16) of row r lies between local cells f-1 and f
-        for (int t = tid; t < ET * (ET + 1); t += ET * ET) {
-            const int r = t / (ET + 1), f = t % (ET + 1);
-            const int y = r + EH, x = f + EH;
-            double st[4][4], F[4];
+        for (int q = 0; q < 4; ++q) u[jj][q][lj][li] = U[q * nc + c];
+    }
+    __syncthreads();
+    for (int t = tid; t < nj * 2 * EFACES; t += ENT) {
+        const int jj = t / (2 * EFACES), r = t % (2 * EFACES);
+        const int d = r / EFACES, k = r % EFACES;
+        double st[4][4], F[4];
+        if (d == 0) {
+            // x-face f (0..8) of row rr lies between local cells f-1 and f
+            const int rr = k / (ET + 1), f = k % (ET + 1);
+            const int y = rr + EH, x = f + EH;
 #pragma unroll
             for (int q = 0; q < 4; ++q) {
-                st[q][0] = u[q][y][x - 2]; st[q][1] = u[q][y][x - 1];
-                st[q][2] = u[q][y][x]; st[q][3] = u[q][y][x + 1];
+                st[q][0] = u[jj][q][y][x - 2]; st[q][1] = u[jj][q][y][x - 1];
+                st[q][2] = u[jj][q][y][x]; st[q][3] = u[jj][q][y][x + 1];
             }
             euler_face_vals(st, 0, a.recon, F);
 #pragma unroll
-            for (int q = 0; q < 4; ++q) fx[q][r][f] = F[q];
-        }
-        for (int t = tid; t < ET * (ET + 1); t += ET * ET) {
-            const int f = t / ET, cidx = t % ET;
+            for (int q = 0; q < 4; ++q) fx[jj][q][rr][f] = F[q];
+        } else {
+            const int f = k / ET, cidx = k % ET;
             const int y = f + EH, x = cidx + EH;
-            double st[4][4], F[4];
 #pragma unroll
             for (int q = 0; q < 4; ++q) {
-                st[q][0] = u[q][y - 2][x]; st[q][1] = u[q][y - 1][x];
-                st[q][2] = u[q][y][x]; st[q][3] = u[q][y + 1][x];
+                st[q][0] = u[jj][q][y - 2][x]; st[q][1] = u[jj][q][y - 1][x];
+                st[q][2] = u[jj][q][y][x]; st[q][3] = u[jj][q][y + 1][x];
             }
             euler_face_vals(st, 1, a.recon, F);
 #pragma unroll
-            for (int q = 0; q < 4; ++q) fy[q][f][cidx] = F[q];
+            for (int q = 0; q < 4; ++q) fy[jj][q][f][cidx] = F[q];
         }
-        __syncthreads();
-        const double c = a.dt * a.cj[jj], idx = 1.0 / a.dx, idy = 1.0 / a.dy;
-#pragma unroll
-        for (int q = 0; q < 4; ++q)
-            s[q] -= c * ((fx[q][ty][tx + 1] - fx[q][ty][tx]) * idx + (fy[q][ty + 1][tx] - fy[q][ty][tx]) * idy);
-        __syncthreads();
     }
+    __syncthreads();
     if (fluid) {
+        const double idx = 1.0 / a.dx, idy = 1.0 / a.dy;
+        double s[4];
+#pragma unroll
+        for (int q = 0; q < 4; ++q) s[q] = a.Un[q * nc + cell];
+        for (int jj = 0; jj < nj; ++jj) {
+            const double c = a.dt * a.cj[jj];
+#pragma unroll
+            for (int q = 0; q < 4; ++q)
+                s[q] -= c * ((fx[jj][q][ty][tx + 1] - fx[jj][q][ty][tx]) * idx +
+                             (fy[jj][q][ty + 1][tx] - fy[jj][q][ty][tx]) * idy);
+        }
 #pragma unroll
         for (int q = 0; q < 4; ++q) a.Uout[q * nc + cell] = s[q];
     }
@@ -440,7 +446,8 @@ __global__ void identity_samples_kernel(int *samples, int nc) {
 
 hipError_t launch_euler(const EulerArgs &a, hipStream_t st) {
     const dim3 grid((unsigned)((a.nx + ET - 1) / ET), (unsigned)((a.ny + ET - 1) / ET));
-    hipLaunchKernelGGL(euler_stage_kernel, grid, dim3(ET * ET), 0, st, a);
+    if (a.nj < 0 || a.nj > ENJ) return hipErrorInvalidValue;
+    hipLaunchKernelGGL(euler_stage_kernel, grid, dim3(ENT), 0, st, a);
     return hipGetLastError();
 }
 
