@@ -46,13 +46,13 @@ ELEM = {"fp64": (8, 8, 8), "fp32": (4, 4, 4), "bf16": (2, 2, 4), "mixed": (4, 2,
 
 
 def kernel_source_digest():
-    """sha256 of the HIP sources: a recorded traffic figure holds only for the
-    kernels it was measured on."""
+    """sha256 of the sources the kinetic stage kernels are built from: a
+    recorded traffic figure holds only for the kernels it was measured on."""
     import hashlib
     csrc = os.path.join(ROOT, "paper_2512_03586_amd", "csrc")
     h = hashlib.sha256()
     for name in sorted(os.listdir(csrc)):
-        if name.endswith((".h", ".hip")):
+        if name in ("device.h", "kernels.h", "kinetic_impl.h") or (name.startswith("kinetic_") and name.endswith(".hip")):
             with open(os.path.join(csrc, name), "rb") as fh:
                 h.update(name.encode() + b"\0" + fh.read())
     return h.hexdigest()
