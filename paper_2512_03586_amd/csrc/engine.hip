@@ -94,7 +94,7 @@ struct Layout {
     size_t f[3], fP, U[4], gp[2], eps, l1, prim, mask, mask_old, cls, kin, buf, newk, blockcounts, counts, err,
         bad, kin_total;
     // learned indicator (indicator == LEARNED only)
-    size_t fields, derived, X, samples, logits, pmask, lcount;
+    size_t derived, pmask, lcount;
     size_t total;
 };
 
@@ -123,11 +123,7 @@ Layout layout(const esbgk_config *c) {
     L.bad = take(sizeof(int));
     L.kin_total = take(sizeof(long long));
     const bool learned = c->indicator == ESBGK_IND_LEARNED;
-    L.fields = take(learned ? 6 * nc * sizeof(double) : 0);
     L.derived = take(learned ? 3 * nc * sizeof(double) : 0);
-    L.X = take(learned ? nc * 192 * sizeof(uint16_t) : 0);
-    L.samples = take(learned ? 2 * nc * sizeof(int) : 0);
-    L.logits = take(learned ? nc * sizeof(float) : 0);
     L.pmask = take(learned ? nc : 0);
     L.lcount = take(learned ? 4 * sizeof(long long) : 0);
     L.total = off;
@@ -160,10 +156,7 @@ struct esbgk_ctx {
     esbgk_mlp *net = nullptr;
     float threshold = 0.0f;
     int dilation = 0;
-    double *lfields = nullptr, *lderived = nullptr;
-    uint16_t *lX = nullptr;
-    int *lsamples = nullptr;
-    float *llogits = nullptr;
+    double *lderived = nullptr;
     uint8_t *pmask = nullptr;
     long long *lcount = nullptr;
     int64_t steps = 0;
@@ -325,20 +318,16 @@ int learned_update(esbgk_ctx *c, hipStream_t st) {
     HIPCHK(launch_prim(c->U[0], c->prim, c->nc, st));
     std::swap(c->mask_old, c->mask);
     IndicatorArgs ia = indicator_args(&c->cfg);
-    ia.prim = c->prim; ia.eps = c->eps; ia.l1 = c->l1; ia.mask_old = c->mask_old; ia.mask_new = c->pmask;
+    ia.U = c->U[0]; ia.eps = c->eps; ia.l1 = c->l1; ia.mask_old = c->mask_old; ia.mask_new = c->pmask;
     HIPCHK(launch_indicator(ia, st));
-    const float *logits = nullptr;
+    long long *counters = c->steps > 0 ? c->lcount : nullptr;
     if (c->net) {
-        HIPCHK(launch_learned_fields(c->prim, c->eps, c->mask_old, c->lfields, c->nc, st));
-        int rc;
-        if ((rc = esbgk_mlp_derived(c->cfg.nx, c->cfg.ny, c->cfg.lx, c->cfg.ly, c->lfields, 1, c->lderived, st)) ||
-            (rc = esbgk_mlp_features(c->cfg.nx, c->cfg.ny, c->lfields, c->lderived, 1, c->lsamples, c->nc, c->lX, st)) ||
-            (rc = esbgk_mlp_forward(c->net, c->lX, c->nc, c->llogits, st)))
-            return fail(rc, "learned indicator: %s", esbgk_mlp_last_error());
-        logits = c->llogits;
+        HIPCHK(launch_learned_mask(c->net, c->cfg.nx, c->cfg.ny, c->cfg.lx, c->cfg.ly, c->prim, c->eps, c->mask_old,
+                                   c->lderived, c->pmask, c->threshold, c->mask, counters, st));
+    } else {
+        HIPCHK(launch_learned_combine(c->pmask, nullptr, 0.0f, c->dilation, c->mask_old, c->mask, c->cls,
+                                      c->cfg.nx, c->cfg.ny, counters, st));
     }
-    HIPCHK(launch_learned_combine(c->pmask, logits, c->threshold, c->net ? 0 : c->dilation, c->mask_old, c->mask,
-                                  c->cls, c->cfg.nx, c->cfg.ny, c->steps > 0 ? c->lcount : nullptr, st));
     return ESBGK_OK;
 }
 
@@ -477,11 +466,7 @@ int esbgk_create(const esbgk_config *cfg, void *d_workspace, size_t bytes, esbgk
     c->bad = (int *)(w + L.bad);
     c->kin_total = (long long *)(w + L.kin_total);
     if (cfg->indicator == ESBGK_IND_LEARNED) {
-        c->lfields = (double *)(w + L.fields);
         c->lderived = (double *)(w + L.derived);
-        c->lX = (uint16_t *)(w + L.X);
-        c->lsamples = (int *)(w + L.samples);
-        c->llogits = (float *)(w + L.logits);
         c->pmask = (uint8_t *)(w + L.pmask);
         c->lcount = (long long *)(w + L.lcount);
     }
@@ -510,10 +495,7 @@ int esbgk_set_state(esbgk_ctx *c, const double *d_rho, const double *d_ux, const
     HIPCHK(hipMemsetAsync(c->mask_old, 0, c->nc, st));
     HIPCHK(hipMemsetAsync(c->l1, 0, c->nc * sizeof(double), st));
     HIPCHK(hipMemsetAsync(c->kin_total, 0, sizeof(long long), st));
-    if (c->lcount) {
-        HIPCHK(hipMemsetAsync(c->lcount, 0, 4 * sizeof(long long), st));
-        HIPCHK(launch_identity_samples(c->lsamples, c->nc, st));
-    }
+    if (c->lcount) HIPCHK(hipMemsetAsync(c->lcount, 0, 4 * sizeof(long long), st));
     if ((rc = regime_lists(c, nullptr, st))) return rc;
     c->steps = 0;
     c->time = 0.0;

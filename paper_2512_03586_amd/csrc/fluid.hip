@@ -382,18 +382,6 @@ static inline unsigned cells_grid(int n) { return (unsigned)((n + 255) / 256 > 0
 
 // ------------------------------------------------- learned indicator glue
 
-// Feature fields of the current state: [6][nc] = (rho, ux, uy, T, eps, mask in use).
-__global__ void learned_fields_kernel(const double *prim, const double *eps, const uint8_t *mask, double *fields,
-                                      int nc) {
-    const int c = blockIdx.x * blockDim.x + threadIdx.x;
-    if (c >= nc) return;
-    const size_t n = (size_t)nc;
-#pragma unroll
-    for (int q = 0; q < 4; ++q) fields[q * n + c] = prim[q * n + c];
-    fields[4 * n + c] = eps[c];
-    fields[5 * n + c] = mask[c] ? 1.0 : 0.0;
-}
-
 __device__ inline void count_add(long long *counters, int q, bool pred) {
     const int n = __syncthreads_count(pred);
     if (threadIdx.x == 0 && n) atomicAdd((unsigned long long *)&counters[q], (unsigned long long)n);
@@ -437,12 +425,6 @@ __global__ void dilate_y_kernel(const uint8_t *tmp, uint8_t *out, int nx, int ny
     out[c] = m;
 }
 
-__global__ void identity_samples_kernel(int *samples, int nc) {
-    const int c = blockIdx.x * blockDim.x + threadIdx.x;
-    if (c >= nc) return;
-    samples[2 * c] = 0;
-    samples[2 * c + 1] = c;
-}
 
 hipError_t launch_euler(const EulerArgs &a, hipStream_t st) {
     const dim3 grid((unsigned)((a.nx + ET - 1) / ET), (unsigned)((a.ny + ET - 1) / ET));
@@ -499,12 +481,6 @@ hipError_t launch_zero_fluid_l1(const uint8_t *mask, double *l1, int nc, hipStre
     return hipGetLastError();
 }
 
-hipError_t launch_learned_fields(const double *prim, const double *eps, const uint8_t *mask, double *fields, int nc,
-                                 hipStream_t st) {
-    hipLaunchKernelGGL(learned_fields_kernel, dim3(cells_grid(nc)), dim3(256), 0, st, prim, eps, mask, fields, nc);
-    return hipGetLastError();
-}
-
 hipError_t launch_learned_combine(const uint8_t *plain, const float *logits, float threshold, int dilation,
                                   const uint8_t *in_use, uint8_t *out, uint8_t *tmp, int nx, int ny,
                                   long long *counters, hipStream_t st) {
@@ -516,9 +492,5 @@ hipError_t launch_learned_combine(const uint8_t *plain, const float *logits, flo
     return hipGetLastError();
 }
 
-hipError_t launch_identity_samples(int *samples, int nc, hipStream_t st) {
-    hipLaunchKernelGGL(identity_samples_kernel, dim3(cells_grid(nc)), dim3(256), 0, st, samples, nc);
-    return hipGetLastError();
-}
 
 }  // namespace esbgk

@@ -100,12 +100,18 @@ hipError_t launch_get_prim(const double *U, double *rho, double *ux, double *uy,
                            hipStream_t st);
 hipError_t launch_accumulate_count(const int *counts, long long *total, hipStream_t st);
 hipError_t launch_zero_fluid_l1(const uint8_t *mask, double *l1, int nc, hipStream_t st);
-hipError_t launch_learned_fields(const double *prim, const double *eps, const uint8_t *mask, double *fields, int nc,
-                                 hipStream_t st);
 hipError_t launch_learned_combine(const uint8_t *plain, const float *logits, float threshold, int dilation,
                                   const uint8_t *in_use, uint8_t *out, uint8_t *tmp, int nx, int ny,
                                   long long *counters, hipStream_t st);
-hipError_t launch_identity_samples(int *samples, int nc, hipStream_t st);
+}  // namespace esbgk
+struct esbgk_mlp;
+namespace esbgk {
+// Learned-indicator check step: derived fields of the current primitives, then
+// mask = plain | (logit > threshold) over the grid; counters (may be null) get
+// the judge counts (missed, extra, plain) and one check.
+hipError_t launch_learned_mask(esbgk_mlp *m, int nx, int ny, double lx, double ly, const double *prim,
+                               const double *eps, const uint8_t *in_use, double *derived, const uint8_t *plain,
+                               float threshold, uint8_t *out, long long *counters, hipStream_t st);
 int scan_positions(int nx, int ny);
 int scan_nblocks(int nx, int ny);
 

@@ -58,20 +58,13 @@ __device__ inline float bf16_val(uint16_t b) { return __uint_as_float((uint32_t)
 
 __device__ inline int wrapm(int i, int n) { i %= n; return i < 0 ? i + n : i; }
 
-// Per-cell e, gA, gB of every snapshot: derived[s][3][nc].
-__global__ void derived_kernel(int nx, int ny, double idx2, double idy2, const double *fields, int nsnap,
-                               double *derived) {
-    const size_t nc = (size_t)nx * ny;
-    const size_t t = blockIdx.x * (size_t)blockDim.x + threadIdx.x;
-    if (t >= nc * nsnap) return;
-    const size_t snap = t / nc;
-    const int c = (int)(t % nc);
+// e, gA, gB of cell c from the fields ux, uy, T, eps (idx2 = 2 dx, idy2 = 2 dy).
+__device__ inline void derived_cell(int nx, int ny, double idx2, double idy2, const double *ux, const double *uy,
+                                    const double *T, const double *eps, int c, double out[3]) {
     const int i = c % nx, j = c / nx;
-    const double *F = fields + snap * 6 * nc;
-    const double *ux = F + nc, *uy = F + 2 * nc, *T = F + 3 * nc, *eps = F + 4 * nc;
     const size_t ce = (size_t)j * nx + wrapm(i + 1, nx), cw = (size_t)j * nx + wrapm(i - 1, nx);
     const size_t cn = (size_t)wrapm(j + 1, ny) * nx + i, cs = (size_t)wrapm(j - 1, ny) * nx + i;
-    // (q_{i+1} - q_{i-1}) / (2 dx), with idx2 = 2 dx
+    // (q_{i+1} - q_{i-1}) / (2 dx)
     const double uxx = (ux[ce] - ux[cw]) / idx2, uxy = (ux[cn] - ux[cs]) / idy2;
     const double uyx = (uy[ce] - uy[cw]) / idx2, uyy = (uy[cn] - uy[cs]) / idy2;
     const double Tx = (T[ce] - T[cw]) / idx2, Ty = (T[cn] - T[cs]) / idy2;
@@ -81,10 +74,38 @@ __global__ void derived_kernel(int nx, int ny, double idx2, double idy2, const d
     const double e2 = e * e;
     const double A = e2 * gu2;
     const double B = (e2 * gT2) / T[c];
+    out[0] = e / (e + 0.01);
+    out[1] = A / (A + 1e-4);
+    out[2] = B / (B + 1e-4);
+}
+
+// Per-cell e, gA, gB of every snapshot: derived[s][3][nc].
+__global__ void derived_kernel(int nx, int ny, double idx2, double idy2, const double *fields, int nsnap,
+                               double *derived) {
+    const size_t nc = (size_t)nx * ny;
+    const size_t t = blockIdx.x * (size_t)blockDim.x + threadIdx.x;
+    if (t >= nc * nsnap) return;
+    const size_t snap = t / nc;
+    const int c = (int)(t % nc);
+    const double *F = fields + snap * 6 * nc;
+    double o[3];
+    derived_cell(nx, ny, idx2, idy2, F + nc, F + 2 * nc, F + 3 * nc, F + 4 * nc, c, o);
     double *D = derived + snap * 3 * nc;
-    D[c] = e / (e + 0.01);
-    D[nc + c] = A / (A + 1e-4);
-    D[2 * nc + c] = B / (B + 1e-4);
+    D[c] = o[0];
+    D[nc + c] = o[1];
+    D[2 * nc + c] = o[2];
+}
+
+// The 7 features of stencil index k (0..24) of cell c (BF16 bits).
+__device__ inline void stencil_features(int nx, int ny, const double *rho, const double *ux, const double *uy,
+                                        const double *T, const double *D, size_t nc, int c, int k, double rc,
+                                        double uxc, double uyc, double Tc, uint16_t out[7]) {
+    const int i = c % nx, j = c / nx;
+    const int dj = k / 5 - 2, di = k % 5 - 2;
+    const size_t s = (size_t)wrapm(j + dj, ny) * nx + wrapm(i + di, nx);
+    const double v[7] = {rho[s] / rc - 1.0, ux[s] - uxc, uy[s] - uyc, T[s] / Tc - 1.0, D[s], D[nc + s], D[2 * nc + s]};
+#pragma unroll
+    for (int m = 0; m < 7; ++m) out[m] = bf16_bits((float)v[m]);
 }
 
 // X[n][192] (BF16 bits) of the samples (snapshot, cell).
@@ -102,19 +123,15 @@ __global__ void features_kernel(int nx, int ny, const double *fields, const doub
         return;
     }
     const size_t snap = (size_t)sn;
-    const int i = c % nx, j = c / nx;
     const double *F = fields + snap * 6 * nc;
     const double *D = derived + snap * 3 * nc;
     const double rc = F[c], uxc = F[nc + c], uyc = F[2 * nc + c], Tc = F[3 * nc + c];
-    for (int dj = -2; dj <= 2; ++dj)
-        for (int di = -2; di <= 2; ++di) {
-            const int k = 5 * (dj + 2) + (di + 2);
-            const size_t s = (size_t)wrapm(j + dj, ny) * nx + wrapm(i + di, nx);
-            const double v[7] = {F[s] / rc - 1.0, F[nc + s] - uxc, F[2 * nc + s] - uyc, F[3 * nc + s] / Tc - 1.0,
-                                 D[s], D[nc + s], D[2 * nc + s]};
+    for (int k = 0; k < 25; ++k) {
+        uint16_t o[7];
+        stencil_features(nx, ny, F, F + nc, F + 2 * nc, F + 3 * nc, D, nc, c, k, rc, uxc, uyc, Tc, o);
 #pragma unroll
-            for (int m = 0; m < 7; ++m) row[7 * k + m] = bf16_bits((float)v[m]);
-        }
+        for (int m = 0; m < 7; ++m) row[7 * k + m] = o[m];
+    }
     row[175] = bf16_bits((float)F[5 * nc + c]);
     for (int m = NF; m < NIN; ++m) row[m] = 0;
 }
@@ -278,6 +295,78 @@ __global__ __launch_bounds__(256) void forward_kernel(Net net, const uint16_t *X
         const float z = forward_tile(L, b3, tid);
         const int row = tile * ROWS + (tid >> 2);
         if ((tid & 3) == 0 && row < n) logits[row] = z;
+    }
+}
+
+// Derived fields of the engine's current state: prim SoA [4][nc], eps [nc].
+__global__ void grid_derived_kernel(int nx, int ny, double idx2, double idy2, const double *prim, const double *eps,
+                                    double *derived) {
+    const size_t nc = (size_t)nx * ny;
+    const int c = (int)(blockIdx.x * blockDim.x + threadIdx.x);
+    if ((size_t)c >= nc) return;
+    double o[3];
+    derived_cell(nx, ny, idx2, idy2, prim + nc, prim + 2 * nc, prim + 3 * nc, eps, c, o);
+    derived[c] = o[0];
+    derived[nc + c] = o[1];
+    derived[2 * nc + c] = o[2];
+}
+
+// Inference over the whole grid for the engine's check step: each 64-cell
+// tile's features are formed in LDS (4 threads per cell; the same operations
+// as features_kernel), the network runs on them, and the mask of the next
+// steps is written directly: out = plain | (logit > threshold).  Counts the
+// judge counters against the mask in use (when counters is given).
+__global__ __launch_bounds__(256) void grid_mask_kernel(Net net, int nx, int ny, const double *prim, const double *eps,
+                                                        const uint8_t *in_use, const double *derived,
+                                                        const uint8_t *plain, float threshold, uint8_t *out,
+                                                        long long *counters) {
+    __shared__ FwdLds L;
+    const int tid = (int)threadIdx.x, row = tid >> 2, part = tid & 3;
+    load_weights_fwd(L, net, tid, 256);
+    const float b3 = net.p[O_B3];
+    const size_t nc = (size_t)nx * ny;
+    const int ntiles = (int)((nc + ROWS - 1) / ROWS);
+    const double *rho = prim, *ux = prim + nc, *uy = prim + 2 * nc, *T = prim + 3 * nc;
+    int cnt[3] = {0, 0, 0};
+    for (int tile = (int)blockIdx.x; tile < ntiles; tile += (int)gridDim.x) {
+        __syncthreads();
+        const int c = tile * ROWS + row;
+        if ((size_t)c < nc) {
+            const double rc = rho[c], uxc = ux[c], uyc = uy[c], Tc = T[c];
+            for (int k = part; k < 25; k += 4) {
+                uint16_t o[7];
+                stencil_features(nx, ny, rho, ux, uy, T, derived, nc, c, k, rc, uxc, uyc, Tc, o);
+#pragma unroll
+                for (int m = 0; m < 7; ++m) L.x[row][7 * k + m] = o[m];
+            }
+            if (part == 0) L.x[row][175] = bf16_bits(in_use[c] ? 1.0f : 0.0f);
+        } else {
+            for (int k = part; k < 25; k += 4)
+#pragma unroll
+                for (int m = 0; m < 7; ++m) L.x[row][7 * k + m] = 0;
+            if (part == 0) L.x[row][175] = 0;
+        }
+        for (int m = NF + part; m < NIN; m += 4) L.x[row][m] = 0;
+        __syncthreads();
+        const float z = forward_tile(L, b3, tid);
+        if (part == 0 && (size_t)c < nc) {
+            const bool p = plain[c], u = in_use[c];
+            out[c] = (uint8_t)(p || z > threshold);
+            cnt[0] += p && !u;
+            cnt[1] += u && !p;
+            cnt[2] += p;
+        }
+    }
+    if (counters) {
+        __shared__ int red[3];
+        if (tid < 3) red[tid] = 0;
+        __syncthreads();
+#pragma unroll
+        for (int q = 0; q < 3; ++q)
+            if (cnt[q]) atomicAdd(&red[q], cnt[q]);
+        __syncthreads();
+        if (tid < 3 && red[tid]) atomicAdd((unsigned long long *)&counters[1 + tid], (unsigned long long)red[tid]);
+        if (tid == 0 && blockIdx.x == 0) atomicAdd((unsigned long long *)&counters[0], 1ull);
     }
 }
 
@@ -515,6 +604,24 @@ int train_tiles(esbgk_mlp *m, const uint16_t *X, const float *y, int n, float wp
 }
 
 }  // namespace
+
+namespace esbgk {
+
+// Check-step inference of the engine (see grid_mask_kernel): derived fields
+// into `derived` (3 nc doubles), then the mask of the next steps.
+hipError_t launch_learned_mask(esbgk_mlp *m, int nx, int ny, double lx, double ly, const double *prim,
+                               const double *eps, const uint8_t *in_use, double *derived, const uint8_t *plain,
+                               float threshold, uint8_t *out, long long *counters, hipStream_t st) {
+    const int nc = nx * ny;
+    hipLaunchKernelGGL(grid_derived_kernel, dim3((nc + 255) / 256), dim3(256), 0, st, nx, ny, 2.0 * (lx / nx),
+                       2.0 * (ly / ny), prim, eps, derived);
+    const int tiles = (nc + ROWS - 1) / ROWS;
+    hipLaunchKernelGGL(grid_mask_kernel, dim3((unsigned)std::min(tiles, 4096)), dim3(256), 0, st, m->net, nx, ny, prim,
+                       eps, in_use, derived, plain, threshold, out, counters);
+    return hipGetLastError();
+}
+
+}  // namespace esbgk
 
 extern "C" {
 
