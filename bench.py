@@ -33,6 +33,8 @@ TRAFFIC_FILE = os.path.join(ROOT, "profiles", "traffic.json")
 WORKLOADS = {
     # name: (generator, kwargs, nx, nv, vmax, steps in the configuration)
     "riemann4": dict(gen="riemann4", nx=256, nv=32, vmax=10.0, kw=dict(seed=0), steps=200),
+    # the learned indicator's evaluation size (trained on 256^2 runs of the same generator)
+    "riemann4_1024": dict(gen="riemann4", nx=1024, nv=32, vmax=10.0, kw=dict(seed=1000), steps=300),
     "shear": dict(gen="shear_modes", nx=512, nv=48, vmax=8.0, kw=dict(seed=0), steps=100),
     "blast": dict(gen="blast", nx=1024, nv=64, vmax=20.0, kw=dict(), steps=200),
 }
@@ -78,7 +80,7 @@ def recorded_traffic(kernel, workload, precision, steps):
 def parse():
     ap = argparse.ArgumentParser()
     ap.add_argument("--gpus", type=int, default=1)
-    ap.add_argument("--steps", type=int, default=200)
+    ap.add_argument("--steps", type=int, default=0, help="timed steps (default: the workload's, 200 or 300)")
     ap.add_argument("--warmup", type=int, default=10)
     ap.add_argument("--precision", default="fp32", choices=["fp32", "bf16", "fp64", "mixed"])
     ap.add_argument("--workload", default="riemann4", choices=sorted(WORKLOADS))
@@ -89,6 +91,10 @@ def parse():
     ap.add_argument("--learned-k", type=int, default=10)
     ap.add_argument("--train-seeds", type=int, default=8)
     ap.add_argument("--no-cpu-baseline", action="store_true")
+    ap.add_argument("--error-vs-fp64", action="store_true",
+                    help="after the timed run, run the FP64 form with the plain indicator (the path the "
+                         "parity tests hold to the oracle at 1e-10) over the same steps and report the "
+                         "relative L1 density error of the timed run against it")
     ap.add_argument("--cpu-steps", type=int, default=16)
     ap.add_argument("--calibrate-copy", type=int, default=0, metavar="MIB",
                     help="first run one plain device-to-device tensor copy of MIB MiB (a kernel of "
@@ -106,7 +112,9 @@ def cpu_baseline(wl, nsteps):
     import oracle
     from paper_2512_03586_amd import inputs
     oracle.build(force=False)
-    nx = wl["nx"]
+    nx = min(wl["nx"], 256)                  # larger grids: a 256^2 slice, same velocity grid
+    if wl["nv"] > 32:
+        nsteps = max(3, nsteps // 4)
     d = getattr(inputs, wl["gen"])(nx=nx, ny=nx, nv=wl["nv"], vmax=wl["vmax"], **wl["kw"])
     p = oracle.Problem(nx=nx, ny=nx, nv=wl["nv"], vmax=wl["vmax"], scheme=1, recon=1, eta=1e-2, delta=1e-3)
     st = oracle.State.from_primitives(p, d["rho"], d["ux"], d["uy"], d["T"], d["eps"])
@@ -145,6 +153,8 @@ def main():
         del src, dst
 
     wl = WORKLOADS[args.workload]
+    if args.steps <= 0:
+        args.steps = wl["steps"]
     prec = {"fp32": E.FP32, "bf16": E.BF16, "fp64": E.FP64, "mixed": E.MIXED}[args.precision]
     es = ELEM[args.precision]
     nx, nv, vmax = wl["nx"], wl["nv"], wl["vmax"]
@@ -159,7 +169,8 @@ def main():
         K = args.learned_k
         if args.indicator == "learned":
             t0 = time.perf_counter()
-            kw = dict(nx=nx, nv=nv, vmax=vmax, steps=wl["steps"] // 2, K=K, precision=prec)
+            # training data: plain runs of the four-quadrant generator at 256^2 x 32^2
+            kw = dict(nx=256, nv=32, vmax=10.0, steps=100, K=K, precision=prec)
             train = LR.collect(range(1, 1 + args.train_seeds), **kw)
             val = LR.collect(range(100, 102), **kw)
             net, res = LR.train(train, val, iters=1500, batch=16384, lr=3e-3, w_pos=4.0, miss=2e-3)
@@ -236,6 +247,18 @@ def main():
         learned_info.update(checks=checks, missed_cell_rate=missed / max(checks * nx * nx, 1),
                             extra_cell_rate=extra / max(checks * nx * nx, 1))
         out["config"]["indicator"] = learned_info
+    if args.error_vs_fp64:
+        rho = eng.moments()[0].double()
+        del eng
+        torch.cuda.empty_cache()
+        ref = E.Engine(E.make_config(nx, nx, nv, vmax, precision=E.FP64, indicator=E.IND_PLAIN, scheme=E.ARS233,
+                                     recon=E.MINMOD2, eta=1e-2, delta=1e-3))
+        ref.set_state(d["rho"], d["ux"], d["uy"], d["T"], d["eps"])
+        ref.step(args.steps)
+        rref = ref.moments()[0].double()
+        out["error_vs_fp64"] = {"rel_l1_rho": float((rho - rref).abs().sum() / rref.abs().sum()),
+                                "reference": "FP64 form, plain indicator every step, same steps from t=0"}
+        del ref
     if not args.no_cpu_baseline:
         out["cpu_baseline"] = cpu_baseline(wl, args.cpu_steps)
     print(json.dumps(out))
