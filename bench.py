@@ -43,7 +43,9 @@ WORKLOADS = {
 # (state arrays f^n / f^{n+1}, stage arrays f^(2), f^(3), partial sum P).  The
 # last implicit stage writes P, the final combination reads P and f^(3).
 PASSES = {"stage2": (1, 1, 0), "stage3": (1, 2, 1), "final": (1, 1, 1)}
-# bytes per value of (state, stage, partial) arrays
+# bytes per value of (state, stage, partial) arrays.  The mixed form stores
+# f^(2) - f^n in BF16, f^(3) in FP32 and P - f^(3) in BF16: per kernel the same
+# byte counts as (4, 2, 4) with f^(3) and P exchanged.
 ELEM = {"fp64": (8, 8, 8), "fp32": (4, 4, 4), "bf16": (2, 2, 4), "mixed": (4, 2, 4)}
 
 
@@ -225,7 +227,7 @@ def main():
         "scaling": "weak",
         "vs_baseline": None,
         "dtype": {"fp32": "f32", "bf16": "bf16-storage/f32", "fp64": "f64",
-                  "mixed": "f32-state/bf16-stages/f32"}[args.precision],
+                  "mixed": "f32-state/bf16-increments/f32"}[args.precision],
         "data": "synthetic",
         "config": {"workload": f"{wl['gen']} {nx}x{nx} cells x {nv}x{nv} velocities on [-{vmax:g},{vmax:g}]^2, "
                                f"ARS(2,3,3), minmod, "

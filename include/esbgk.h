@@ -62,9 +62,11 @@ enum { ESBGK_COUPLE_STAGE = 0, ESBGK_COUPLE_STEP = 1 };       /* coupling */
  *              kinetic transport (the Lax-Friedrichs flux of Sec. 3.2 with
  *              dissipation |v|), Rusanov flux for Euler.
  *  precision   storage and arithmetic of f: FP64; FP32; BF16 storage with
- *              FP32 arithmetic; or MIXED: the state f^n in FP32 and the two
- *              intermediate stage arrays in BF16, FP32 arithmetic (ARS(2,3,3)
- *              only).  FP32 velocity sums are compensated.  Per-cell
+ *              FP32 arithmetic; or MIXED: the state f^n in FP32, FP32
+ *              arithmetic, and 16-bit storage of two increments, f^(2) - f^n
+ *              and P - f^(3) (P the partial sum of the final combination,
+ *              f^(3) kept in FP32), ARS(2,3,3) only.  FP32 velocity sums are
+ *              compensated.  Per-cell
  *              quantities are FP64 always, and so are the 2x2 ES-tensor
  *              algebra and the 6x6 conservation solve.
  *  indicator   PLAIN: the breakdown criteria of Sec. 3.1.2 every step;

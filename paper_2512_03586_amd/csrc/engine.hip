@@ -13,6 +13,7 @@
 #include <algorithm>
 #include <cmath>
 #include <new>
+#include <type_traits>
 #include <vector>
 
 #include "../../include/esbgk.h"
@@ -213,9 +214,10 @@ int regime_lists(esbgk_ctx *c, const uint8_t *mask_old, hipStream_t st, long lon
 }
 
 template <class S> int fill_list(esbgk_ctx *c, void *f, const double *U, const int *list, const int *count,
-                                 hipStream_t st) {
+                                 hipStream_t st, const void *ref_in = nullptr) {
     FillArgs<S> a;
     a.g = c->g; a.U = U; a.f = (S *)f; a.list = list; a.count = count; a.err = c->err; a.nc = c->nc;
+    a.ref_in = (const float *)ref_in;
     TimedLaunch tl(c, ESBGK_K_FILL, st);
     HIPCHK(launch_fill<S>(a, c->nc, st));
     HIPCHK(tl.done());
@@ -257,6 +259,10 @@ template <class SN, class SS> int kinetic_stage(esbgk_ctx *c, int i, hipStream_t
     a.Uout = Uout;
     a.l1out = c->l1;
     const bool partial = c->cfg.scheme == ESBGK_ARS233;
+    // mixed form (FP32 state, BF16 stage arrays): increment storage -- f^(2) is
+    // stored as f^(2) - f^n; stage 3 writes f^(3) in FP32 into the partial-sum
+    // buffer and P - f^(3) into the BF16 array of f^(3)
+    const bool inc = !std::is_same<SN, SS>::value;
     if (i < 3) {
         a.fn = c->f[0];
         const double *rowt = &c->At[3 * i], *rowi = &c->A[3 * i];
@@ -274,13 +280,15 @@ template <class SN, class SS> int kinetic_stage(esbgk_ctx *c, int i, hipStream_t
             if (a.nq != 1 || c->b[0] != 0.0) return fail(ESBGK_EINVAL, "tableau not supported by the partial sum");
             a.sout = c->fP;
             a.scq = c->b[1];
+            if (inc) std::swap(a.fout, a.sout);  // f^(3) in FP32, P - f^(3) in the BF16 stage array
         }
         // ARS(2,2,2) is stiffly accurate: its last stage is f^{n+1}
         a.emit = (i == 2 && c->cfg.scheme == ESBGK_ARS222) ? 1 : 0;
     } else {
-        a.fn = c->fP;
-        a.fl[0] = c->f[2]; a.cl[0] = c->bt[2]; a.nl = 1;
-        a.fq[0] = c->f[2]; a.pq[0] = c->gp[1]; a.cq[0] = c->b[2]; a.nq = 1;
+        void *f3 = inc ? c->fP : c->f[2], *part = inc ? c->f[2] : c->fP;
+        a.fn = part;
+        a.fl[0] = f3; a.cl[0] = c->bt[2]; a.nl = 1;
+        a.fq[0] = f3; a.pq[0] = c->gp[1]; a.cq[0] = c->b[2]; a.nq = 1;
         a.aii = 0.0;
         a.fout = c->f[0];  // f^n is not read by the final combination
         a.emit = 1;
@@ -366,7 +374,14 @@ template <class SN, class SS> int run_step(esbgk_ctx *c, hipStream_t st) {
         if ((rc = euler_stage(c, i, st, c->U[i]))) return rc;
         if (!last222) {
             const double *Ub = loc ? c->U[0] : c->U[i];
-            if ((rc = fill_list<SS>(c, c->f[i], Ub, c->buf, c->counts + 1, st))) return rc;
+            // mixed form: the BF16 array f^(2) holds f^(2) - f^n; f^(3) is kept in FP32
+            // in the partial-sum buffer (see kinetic_stage)
+            if (!std::is_same<SN, SS>::value && i == 2) {
+                if ((rc = fill_list<SN>(c, c->fP, Ub, c->buf, c->counts + 1, st))) return rc;
+            } else if ((rc = fill_list<SS>(c, c->f[i], Ub, c->buf, c->counts + 1, st,
+                                           std::is_same<SN, SS>::value ? nullptr : c->f[0]))) {
+                return rc;
+            }
         }
     }
     if (c->cfg.scheme == ESBGK_ARS233) {

@@ -8,7 +8,10 @@ namespace esbgk {
 // Arrays of f are of the state's storage type SN (f^n, and f^{n+1} written by
 // the final combination) or of the stage arrays' type SS (f^(2), f^(3)); the
 // kernels cast them.  The first transported array of an implicit stage is
-// f^n, every other transported array is a stage array.
+// f^n, every other transported array is a stage array.  In the mixed form
+// (SN = float, SS = bf16_t) the BF16 arrays hold increments: fl[1] of stage 3
+// is f^(2) - f^n; stage 3 writes f^(3) (FP32) to fout and P - f^(3) (BF16)
+// to sout, and the final combination reads them as fl[0] and fn.
 struct StageArgs {
     Geom g;
     const void *fn;                                        // f^n: base value at the cell
@@ -35,6 +38,9 @@ template <class S> struct FillArgs {
     Geom g;
     const double *U;
     S *f;
+    // mixed form: the BF16 array f^(2) holds f^(2) - f^n; given ref_in (f^n),
+    // the fill stores Mhat(U) - ref_in
+    const float *ref_in;
     const int *list;
     const int *count;
     int *err;

@@ -38,6 +38,7 @@
 #define ESBGK_FINAL_MIN_WAVES 4
 #endif
 
+
 namespace esbgk {
 
 __device__ inline int wrapi(int i, int n) { i %= n; return i < 0 ? i + n : i; }
@@ -359,10 +360,32 @@ template <class T, int C> __host__ __device__ constexpr int waves_per_block() {
     return 4 * (2 * C * 64 * 4 * (int)sizeof(T)) <= 80 * 1024 ? 4 : 1;
 }
 
-template <class T, int C> struct StageLds {
-    static constexpr int W = waves_per_block<T, C>();
+// Stage kernels: the implicit stages stage f* and the sampled Gaussian, the
+// final combination f* only.  The mixed form's last implicit stage also keeps
+// P until f^(3) is known: in LDS while three arrays of four waves fit in
+// 80 KB (nv <= 32), else in the FP32 buffer f^(3) is written to (the wave
+// reads back its own write, from L2).  Four waves per block when the block's
+// LDS stays within 80 KB, else one.
+template <class T, int C> __host__ __device__ constexpr bool p_in_lds() {
+    return 4 * 3 * C * 64 * 4 * (int)sizeof(T) <= 80 * 1024;
+}
+template <class T, int C, bool FINAL, bool KEEP_P> __host__ __device__ constexpr int stage_waves() {
+    return 4 * (FINAL ? 1 : (KEEP_P && p_in_lds<T, C>()) ? 3 : 2) * C * 64 * 4 * (int)sizeof(T) <= 80 * 1024 ? 4
+                                                                                                           : 1;
+}
+
+// Optional LDS arrays, as (possibly empty) bases so that an absent one takes no space.
+template <class T, int W, int C, bool ON> struct LdsGauss { T g[W][C][64][4]; };  // sampled Gaussian
+template <class T, int W, int C> struct LdsGauss<T, W, C, false> {};
+template <class T, int W, int C, bool ON> struct LdsPartial { T p[W][C][64][4]; };  // P until f^(3) is known
+template <class T, int W, int C> struct LdsPartial<T, W, C, false> {};
+
+template <class T, int C, bool FINAL, bool KEEP_P>
+struct StageLds : LdsGauss<T, stage_waves<T, C, FINAL, KEEP_P>(), C, !FINAL>,
+                  LdsPartial<T, stage_waves<T, C, FINAL, KEEP_P>(), C, KEEP_P && p_in_lds<T, C>()> {
+    static constexpr int W = stage_waves<T, C, FINAL, KEEP_P>();
+    static constexpr bool P = KEEP_P && p_in_lds<T, C>();
     T v[W][C][64][4];  // [wave in block][chunk][lane][node]: f*
-    T g[W][C][64][4];  // sampled Gaussian of the relaxed state
 };
 
 // The discrete-conservation correction of a sampled Gaussian (a reading: the
@@ -474,16 +497,52 @@ template <class T> __device__ constexpr double correction_tol() { return sizeof(
 template <class S> struct PartialOf { using type = S; };
 template <> struct PartialOf<bf16_t> { using type = float; };
 
+// Increment storage of the mixed form (FP32 state, 16-bit stage storage):
+// each BF16 array holds a difference to an FP32 array that its reader reads at
+// the same nodes anyway, so the rounding error is relative to an increment of
+// one stage rather than to f, at the HBM traffic of plain BF16 stage arrays.
+//   f^(2) is stored as f^(2) - f^n (stage 3 transports f^n at the same stencil);
+//   stage 3 stores f^(3) in FP32 and the partial sum as P - f^(3) (the final
+//   combination reads f^(3) at the stencil and P only at the cell).
+// Buffer cells are filled to match (f^(2): Mhat(U) - f^n; f^(3): Mhat(U)).
+template <class SN, class SS> __host__ __device__ constexpr bool increment_storage() {
+    return !std::is_same<SN, SS>::value;
+}
+
+// dst += src over the stencil entries load_stencil fills for chunk ch.
+template <class T, int RECON> __device__ inline void add_stencil(Stencil<T> &dst, const Stencil<T> &src,
+                                                                const Chunk<T> &ch) {
+#pragma unroll
+    for (int e = 0; e < 4; ++e) {
+        dst.c[e] += src.c[e];
+        dst.y[0][e] += src.y[0][e];
+        dst.x[0][e] += src.x[0][e];
+        if (RECON != 0) {
+            dst.y[1][e] += src.y[1][e];
+            dst.y[2][e] += src.y[2][e];
+            dst.x[2][e] += src.x[2][e];
+        }
+        if (RECON != 0 || ch.straddle) dst.x[1][e] += src.x[1][e];
+        if (RECON != 0 && ch.straddle) dst.x[3][e] += src.x[3][e];
+    }
+}
+
 template <class SN, class SS, int NV, int L, int C, int NL, int NQ, bool FINAL, int RECON, bool SIDE>
-__global__ __launch_bounds__((64 * waves_per_block<typename Storage<SN>::T, C>()),
+__global__ __launch_bounds__((64 * stage_waves<typename Storage<SN>::T, C, FINAL,
+                                                (SIDE && increment_storage<SN, SS>())>()),
                              (FINAL ? ESBGK_FINAL_MIN_WAVES : ESBGK_STAGE_MIN_WAVES)) void stage_kernel(
     StageArgs a) {
     using T = typename Storage<SN>::T;
     using SP = typename PartialOf<SN>::type;
     static_assert(std::is_same<T, typename Storage<SS>::T>::value, "one arithmetic type per kernel");
-    __shared__ StageLds<T, C> lds;
+    constexpr bool INC = increment_storage<SN, SS>();
+    static_assert(!INC || std::is_same<SP, T>::value, "increments are taken over state-precision arrays");
+    static_assert(!INC || ESBGK_PREFETCH, "increment storage completes stencils in the prefetch buffer");
+    constexpr bool KEEP_P = SIDE && INC;
+    using Lds = StageLds<T, C, FINAL, KEEP_P>;
+    __shared__ Lds lds;
     const Geom &g = a.g;
-    const GroupCell gc = group_cell<L, waves_per_block<T, C>()>(a.list, *a.count);
+    const GroupCell gc = group_cell<L, Lds::W>(a.list, *a.count);
     if (gc.cell < 0) return;
     const int cell = gc.cell;
     const int lane = (int)(threadIdx.x & 63), wave = (int)(threadIdx.x >> 6);
@@ -549,7 +608,14 @@ __global__ __launch_bounds__((64 * waves_per_block<typename Storage<SN>::T, C>()
                 T pv[4];
 #pragma unroll
                 for (int e = 0; e < 4; ++e) pv[e] = (base[e] - dt * pacc[e]) + psum[e];
-                Storage<SP>::store4((SP *)a.sout + nb.c, (uint32_t)ch.k0, pv);
+                if constexpr (Lds::P) {
+#pragma unroll
+                    for (int e = 0; e < 4; ++e) lds.p[wave][m][lane][e] = pv[e];
+                } else if constexpr (KEEP_P) {
+                    Storage<SP>::store4((SP *)a.fout + nb.c, (uint32_t)ch.k0, pv);  // read back in the relaxation
+                } else {
+                    Storage<SP>::store4((SP *)a.sout + nb.c, (uint32_t)ch.k0, pv);
+                }
             }
         }
     };
@@ -566,9 +632,23 @@ __global__ __launch_bounds__((64 * waves_per_block<typename Storage<SN>::T, C>()
             if (!ch.active) return;
             if (!FINAL && l == 0)
                 load_stencil<SN, RECON>((const SN *)a.fl[0], nb, ch, sb[slot]);
+            else if (FINAL && INC)
+                load_stencil<SP, RECON>((const SP *)a.fl[0], nb, ch, sb[slot]);  // f^(3) in FP32
             else
                 load_stencil<SS, RECON>((const SS *)a.fl[l], nb, ch, sb[slot]);
-            if (FINAL && l == 0) Storage<SP>::load4((const SP *)a.fn + nb.c, (uint32_t)ch.k0, sb[slot].b);
+            if (FINAL && INC)
+                Storage<SS>::load4((const SS *)a.fn + nb.c, (uint32_t)ch.k0, sb[slot].b);  // P - f^(3)
+            else if (FINAL)
+                Storage<SP>::load4((const SP *)a.fn + nb.c, (uint32_t)ch.k0, sb[slot].b);
+        };
+        // Increment storage, stage 3: the loaded f^(2) - f^n of unit u (its
+        // chunk's second unit) plus f^n, the stencil of the unit before.
+        auto complete_unit = [&](int u) {
+            if constexpr (INC && !FINAL) {
+                const int m = u / NL, l = u % NL;
+                const Chunk<T> ch = chunk_of<T, L, NV>(s, m, g);
+                if (ch.active && l == 1) add_stencil<T, RECON>(sb[u & 1], sb[(u - 1) & 1], ch);
+            }
         };
         if (PF) load_unit(0, 0);
 #pragma unroll
@@ -585,12 +665,14 @@ __global__ __launch_bounds__((64 * waves_per_block<typename Storage<SN>::T, C>()
             if (ch.active) {
                 if (l == 0) {
 #pragma unroll
-                    for (int e = 0; e < 4; ++e) base[e] = FINAL ? cur.b[e] : cur.c[e];  // stages transport f^n first
+                    for (int e = 0; e < 4; ++e)  // stages transport f^n first; the final combination's base is P
+                        base[e] = !FINAL ? cur.c[e] : INC ? cur.c[e] + cur.b[e] : cur.b[e];
                 }
                 T Lt[4];
                 transport_of<T, RECON>(cur, ch, idx, idy, Lt);
                 unit_body(m, l, ch, Lt, cur.c);
             }
+            if (INC && !FINAL && u + 1 < NU) complete_unit(u + 1);
             if (l == NL - 1 && (m & 3) == 3) macc.fold();
             // bounded register use: at most two units' loads live at a time
             __builtin_amdgcn_sched_barrier(0);
@@ -636,6 +718,7 @@ __global__ __launch_bounds__((64 * waves_per_block<typename Storage<SN>::T, C>()
         const double pref = gp[GP_PREF];
 #pragma unroll
         for (int q = 0; q < 6; ++q) gp[GP_C0 + q] = pref * ((q == 0 ? 1.0 : 0.0) + dc[q]);
+
         // ---- relaxation: f = (f* + lam Gtilde (1 + dc . psi)) / (1 + lam), the stage's single write
         const T d0 = (T)dc[0], d1 = (T)dc[1], d2 = (T)dc[2], d3 = (T)dc[3], d4 = (T)dc[4], d5 = (T)dc[5];
 #pragma unroll
@@ -644,14 +727,32 @@ __global__ __launch_bounds__((64 * waves_per_block<typename Storage<SN>::T, C>()
             if (ch.active) {
                 const T b = (ch.vy - ge.uy) * ge.ist;
                 const T plin = d1 + d4 * b, pconst = d0 + (d2 + d5 * b) * b;
-                T fv[4];
+                // mixed form: the reference of the stored increment (stage 2: f^n; stage 3: P)
+                T rv[4] = {0, 0, 0, 0};
+                if constexpr (Lds::P) {
+#pragma unroll
+                    for (int e = 0; e < 4; ++e) rv[e] = lds.p[wave][m][lane][e];
+                } else if constexpr (KEEP_P) {
+                    Storage<SP>::load4((const SP *)a.fout + nb.c, (uint32_t)ch.k0, rv);
+                } else if constexpr (INC) {
+                    Storage<SN>::load4((const SN *)a.fn + nb.c, (uint32_t)ch.k0, rv);
+                }
+                T fv[4], sv[4];
 #pragma unroll
                 for (int e = 0; e < 4; ++e) {
                     const T aa = (ch.vx[e] - ge.ux) * ge.ist;
                     const T Ghat = lds.g[wave][m][lane][e] * ((T)1 + ((d3 * aa + plin) * aa + pconst));
                     fv[e] = (lds.v[wave][m][lane][e] + lamt * Ghat) * inv1;
+                    sv[e] = !INC ? fv[e] : KEEP_P ? rv[e] - fv[e] : fv[e] - rv[e];
                 }
-                if (gc.valid) Storage<SS>::store4((SS *)a.fout + nb.c, (uint32_t)ch.k0, fv);
+                if (gc.valid) {
+                    if constexpr (KEEP_P) {
+                        Storage<SP>::store4((SP *)a.fout + nb.c, (uint32_t)ch.k0, fv);   // f^(3)
+                        Storage<SS>::store4((SS *)a.sout + nb.c, (uint32_t)ch.k0, sv);   // P - f^(3)
+                    } else {
+                        Storage<SS>::store4((SS *)a.fout + nb.c, (uint32_t)ch.k0, sv);
+                    }
+                }
                 if (want_l1) {
                     const T ey = ch.vy - uyt, qy = mq * ey * ey;
 #pragma unroll
@@ -738,6 +839,15 @@ __global__ __launch_bounds__((64 * waves_per_block<typename Storage<S>::T, C>())
                 const T aa = (ch.vx[e] - ge.ux) * ge.ist;
                 const T G = glds[wave][m][lane][e];
                 v[e] = G + G * ((d3 * aa + plin) * aa + pconst);
+            }
+            if constexpr (std::is_same<S, bf16_t>::value) {
+                // increment storage of a stage array (see increment_storage)
+                if (a.ref_in) {
+                    T r[4];
+                    Storage<float>::load4(a.ref_in + (size_t)cell * g.nv2, (uint32_t)ch.k0, r);
+#pragma unroll
+                    for (int e = 0; e < 4; ++e) v[e] -= r[e];
+                }
             }
             Storage<S>::store4(a.f + (size_t)cell * g.nv2, (uint32_t)ch.k0, v);
         }
@@ -844,7 +954,8 @@ static hipError_t stage_dispatch(const StageArgs &a, int nmax, hipStream_t st) {
     const Shape sh = shape_for(a.g.nv2);
 #define ESBGK_CASE(NN, LL, CC)                                                                                     \
     if ((NN == 0) ? (sh.L == LL && sh.C == CC) : (a.g.nv == NN)) {                                                    \
-        constexpr int WPB = waves_per_block<typename Storage<SN>::T, CC>();                                         \
+        constexpr int WPB = stage_waves<typename Storage<SN>::T, CC, FINAL,                                         \
+                                        (SIDE && increment_storage<SN, SS>())>();                                   \
         const dim3 grid(grid_for(nmax, WPB * (64 / LL))), block(64 * WPB);                                          \
         if (a.g.recon == 0)                                                                                         \
             hipLaunchKernelGGL((stage_kernel<SN, SS, NN, LL, CC, NL, NQ, FINAL, 0, SIDE>), grid, block, 0, st, a);  \
@@ -865,6 +976,8 @@ hipError_t launch_stage(const StageArgs &a, int nmax, hipStream_t st) {
         if (a.nl - a.nq + q < 0 || a.fq[q] != a.fl[a.nl - a.nq + q]) return hipErrorInvalidValue;
     if (a.aii > 0.0) {
         if (a.nl < 1 || a.fl[0] != a.fn) return hipErrorInvalidValue;  // implicit stages transport f^n first
+        // increment storage: the increment of the second implicit stage is taken over the partial sum
+        if (increment_storage<SN, SS>() && a.nl == 2 && !a.sout) return hipErrorInvalidValue;
         if (a.nl == 1 && a.nq == 0 && !a.sout) return stage_dispatch<SN, SS, 1, 0, false, false>(a, nmax, st);
         if (a.nl == 2 && a.nq == 1 && !a.sout) return stage_dispatch<SN, SS, 2, 1, false, false>(a, nmax, st);
         if (a.nl == 2 && a.nq == 1 && a.sout) return stage_dispatch<SN, SS, 2, 1, false, true>(a, nmax, st);

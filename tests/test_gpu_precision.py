@@ -4,7 +4,7 @@ The shear-layer workload (512^2 cells x 48^2 velocities on [-8, 8]^2, eps = 1e-3
 ARS(2,3,3), minmod, 100 steps) is run on a downsampled copy: 128^2 cells with
 the same velocity grid and the same time-step rule, for 25 steps, which is the
 same physical time.  The FP64 oracle and the GPU engine with f stored in FP64,
-FP32, BF16 and the mixed form (f^n in FP32, the two stage arrays in BF16)
+FP32, BF16 and the mixed form (FP32 state, BF16 increments in the stage arrays)
 run the same problem with the regime update on.  A fully
 kinetic 64^2 x 48^2 copy makes the stored-precision error visible in every
 cell (in the coupled run only the two shear layers are kinetic).
@@ -18,12 +18,12 @@ stage values fully) 3e-3, 1.6e-2 and 2.5e-3 on rho, u and T.  (Rounding the orac
 points gives 1.2e-4 on rho in the coupled run: the bar is that error with a
 margin, and the GPU's error is of that size.)  These are reported results,
 not pins: the paper fixes no value for them.  The mixed form keeps the
-state in FP32, so storage rounding enters each step only through the stage
-values (the oracle rounded at the same points gives 4.3e-5 on rho in the
-coupled run); its bars are 1e-4 on rho and 1e-3 on u and T in the coupled
-run, and 2e-3, 1e-2, 1.5e-3 in the fully kinetic one.  The fully kinetic bars
-are about twice the measured errors (BF16 1.5e-3, 8.2e-3, 1.2e-3; mixed
-9.2e-4, 4.7e-3, 7.4e-4).
+state in FP32 and stores only increments in BF16 (f^(2) - f^n, and P - f^(3)
+with f^(3) itself in FP32), so the 8-bit rounding applies to the change over
+one stage rather than to f; it is held to the FP32 path's bars, 2e-5 on rho, u
+and T in both runs (measured 3.6e-8, 1.3e-7, 3.1e-8 coupled and 4.3e-7,
+1.5e-6, 3.1e-7 fully kinetic).  The fully kinetic BF16 bars are about twice
+the measured errors (1.5e-3, 8.2e-3, 1.2e-3).
 Setting ESBGK_REPORT_DIR writes the table there as JSON.
 """
 import json
@@ -100,9 +100,9 @@ def kinetic():
 
 
 BARS_COUPLED = {"fp64": (1e-10, 1e-10, 1e-10), "fp32": (2e-5, 2e-5, 2e-5), "bf16": (2e-4, 1e-3, 1e-3),
-                "mixed": (1e-4, 1e-3, 1e-3)}
+                "mixed": (2e-5, 2e-5, 2e-5)}
 BARS_KINETIC = {"fp64": (1e-10, 1e-10, 1e-10), "fp32": (2e-5, 2e-5, 2e-5), "bf16": (3e-3, 1.6e-2, 2.5e-3),
-                "mixed": (2e-3, 1e-2, 1.5e-3)}
+                "mixed": (2e-5, 2e-5, 2e-5)}
 PRECISION = {"fp64": 0, "fp32": 1, "bf16": 2, "mixed": 3}
 FORMS = ["fp64", "fp32", "bf16", "mixed"]
 
