@@ -92,6 +92,8 @@ def parse():
                          "dilated: the plain check every K steps with its mask dilated")
     ap.add_argument("--learned-k", type=int, default=10)
     ap.add_argument("--train-seeds", type=int, default=8)
+    ap.add_argument("--learned-miss", type=float, default=2e-3,
+                    help="threshold: the fraction of held-out positive cells allowed below it")
     ap.add_argument("--no-cpu-baseline", action="store_true")
     ap.add_argument("--error-vs-fp64", action="store_true",
                     help="after the timed run, run the FP64 form with the plain indicator (the path the "
@@ -175,10 +177,11 @@ def main():
             kw = dict(nx=256, nv=32, vmax=10.0, steps=100, K=K, precision=prec)
             train = LR.collect(range(1, 1 + args.train_seeds), **kw)
             val = LR.collect(range(100, 102), **kw)
-            net, res = LR.train(train, val, iters=1500, batch=16384, lr=3e-3, w_pos=4.0, miss=2e-3)
+            net, res = LR.train(train, val, iters=1500, batch=16384, lr=3e-3, w_pos=4.0, miss=args.learned_miss)
             torch.cuda.synchronize()
             eng.set_learned(net, res.threshold)
-            learned_info = {"K": K, "train_seeds": args.train_seeds, "train_seconds_incl_data": round(time.perf_counter() - t0, 2),
+            learned_info = {"K": K, "train_seeds": args.train_seeds, "miss_quantile": args.learned_miss,
+                            "train_seconds_incl_data": round(time.perf_counter() - t0, 2),
                             "threshold": res.threshold, "val_recall": res.val_recall}
         else:
             eng.set_learned(None, 0.0, LR.dilation_radius(K))
