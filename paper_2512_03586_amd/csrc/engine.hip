@@ -92,7 +92,7 @@ int validate(const esbgk_config *c) {
 }
 
 struct Layout {
-    size_t f[3], fP, U[4], gp[2], eps, l1, prim, mask, mask_old, cls, kin, buf, newk, blockcounts, counts, err,
+    size_t f[3], fP, U[4], gp, eps, l1, prim, mask, mask_old, cls, kin, buf, newk, blockcounts, counts, err,
         bad, kin_total;
     // learned indicator (indicator == LEARNED only)
     size_t derived, pmask, lcount;
@@ -108,7 +108,8 @@ Layout layout(const esbgk_config *c) {
     // partial sum of the final combination (ARS(2,3,3)), state precision and at least FP32
     L.fP = take(c->scheme == ESBGK_ARS233 ? nc * nv2 * std::max<size_t>(4, state_elem(c->precision)) : 0);
     for (int q = 0; q < 4; ++q) L.U[q] = take(4 * nc * sizeof(double));
-    for (int q = 0; q < 2; ++q) L.gp[q] = take((size_t)GP_N * nc * sizeof(double));
+    // Gaussian parameters of stage 2, read by stage 3 when the stage arrays are BF16
+    L.gp = take(stage_elem(c->precision) == 2 ? (size_t)GP_N * nc * sizeof(double) : 0);
     L.eps = take(nc * sizeof(double));
     L.l1 = take(nc * sizeof(double));
     L.prim = take(4 * nc * sizeof(double));
@@ -147,7 +148,7 @@ struct esbgk_ctx {
     void *f[3]{};
     void *fP = nullptr;
     double *U[4]{};
-    double *gp[2]{};
+    double *gp = nullptr;  // BF16 stage arrays only
     double *eps = nullptr, *l1 = nullptr, *prim = nullptr;
     uint8_t *mask = nullptr, *mask_old = nullptr, *cls = nullptr;
     int *kin = nullptr, *buf = nullptr, *newk = nullptr, *blockcounts = nullptr, *counts = nullptr,
@@ -247,10 +248,14 @@ IndicatorArgs indicator_args(const esbgk_config *cfg) {
 }
 
 // One IMEX stage (i = 1, 2) or the final combination (i = 3) on kinetic cells.
+// An implicit term dt A_ij Q'_j of an earlier stage is taken as
+// (A_ij / A_jj)(f^(j) - f*_j), f*_j rebuilt from the transport of f^n, which
+// for the exact relaxation of stage j equals dt A_ij (tau/eps)(Ghat_j - f^(j)).
 // With ARS(2,3,3) the last implicit stage also writes the partial sum
-//   P = f^n - dt sum_{j<3} bt_j L(f^(j)) + dt sum_{j<3} b_j Q'_j
-// (its transport and implicit terms are the ones the stage computes anyway),
-// and the final combination is f^{n+1} = P - dt bt_3 L(f^(3)) + dt b_3 Q'_3.
+//   P' = f^n - dt sum_{j<3} bt_j L(f^(j)) + dt sum_{j<=3} b_j Q'_j
+// (its transport and implicit terms are the ones the stage computes anyway,
+// Q'_3 = (f^(3) - f*_3)/(dt A_33) once f^(3) is known), and the final
+// combination is f^{n+1} = P' - dt bt_3 L(f^(3)).
 template <class SN, class SS> int kinetic_stage(esbgk_ctx *c, int i, hipStream_t st, double *Uout) {
     StageArgs a;
     memset(&a, 0, sizeof a);
@@ -271,16 +276,23 @@ template <class SN, class SS> int kinetic_stage(esbgk_ctx *c, int i, hipStream_t
                 a.fl[a.nl] = c->f[j]; a.cl[a.nl] = rowt[j]; a.scl[a.nl] = c->bt[j]; ++a.nl;
             }
         for (int j = 1; j < i; ++j)
-            if (rowi[j] != 0.0) { a.fq[a.nq] = c->f[j]; a.pq[a.nq] = c->gp[j - 1]; a.cq[a.nq] = rowi[j]; ++a.nq; }
+            if (rowi[j] != 0.0) {
+                // f*_j of stage j = 2 involves f^n only (A_21 = 0)
+                if (j != 1 || a.nq != 0 || c->A[3] != 0.0 || !(c->A[4] > 0.0))
+                    return fail(ESBGK_EINVAL, "tableau not supported by the kinetic stage kernels");
+                a.fq[0] = c->f[j]; a.qa = rowi[j]; a.qd = c->A[3 * j + j]; a.ctn = c->At[3 * j]; ++a.nq;
+                a.qb = c->b[j];
+                a.pq = c->gp;
+            }
         a.aii = c->A[3 * i + i];
         a.fout = c->f[i];
-        a.pout = c->gp[i - 1];
+        if (i == 1) a.pout = c->gp;  // null unless the stage arrays are BF16
         if (partial && i == 2) {
             // the one implicit term of stage 3 is that of stage 2
             if (a.nq != 1 || c->b[0] != 0.0) return fail(ESBGK_EINVAL, "tableau not supported by the partial sum");
             a.sout = c->fP;
-            a.scq = c->b[1];
-            if (inc) std::swap(a.fout, a.sout);  // f^(3) in FP32, P - f^(3) in the BF16 stage array
+            a.sfin = c->b[2] / c->A[8];
+            if (inc) std::swap(a.fout, a.sout);  // f^(3) in FP32, P' - f^(3) in the BF16 stage array
         }
         // ARS(2,2,2) is stiffly accurate: its last stage is f^{n+1}
         a.emit = (i == 2 && c->cfg.scheme == ESBGK_ARS222) ? 1 : 0;
@@ -288,7 +300,6 @@ template <class SN, class SS> int kinetic_stage(esbgk_ctx *c, int i, hipStream_t
         void *f3 = inc ? c->fP : c->f[2], *part = inc ? c->f[2] : c->fP;
         a.fn = part;
         a.fl[0] = f3; a.cl[0] = c->bt[2]; a.nl = 1;
-        a.fq[0] = f3; a.pq[0] = c->gp[1]; a.cq[0] = c->b[2]; a.nq = 1;
         a.aii = 0.0;
         a.fout = c->f[0];  // f^n is not read by the final combination
         a.emit = 1;
@@ -465,7 +476,7 @@ int esbgk_create(const esbgk_config *cfg, void *d_workspace, size_t bytes, esbgk
     for (int q = 0; q < 3; ++q) c->f[q] = w + L.f[q];
     c->fP = w + L.fP;
     for (int q = 0; q < 4; ++q) c->U[q] = (double *)(w + L.U[q]);
-    for (int q = 0; q < 2; ++q) c->gp[q] = (double *)(w + L.gp[q]);
+    c->gp = stage_elem(cfg->precision) == 2 ? (double *)(w + L.gp) : nullptr;
     c->eps = (double *)(w + L.eps);
     c->l1 = (double *)(w + L.l1);
     c->prim = (double *)(w + L.prim);

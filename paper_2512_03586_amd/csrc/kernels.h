@@ -12,20 +12,31 @@ namespace esbgk {
 // (SN = float, SS = bf16_t) the BF16 arrays hold increments: fl[1] of stage 3
 // is f^(2) - f^n; stage 3 writes f^(3) (FP32) to fout and P - f^(3) (BF16)
 // to sout, and the final combination reads them as fl[0] and fn.
+// The implicit term dt A_ij Q'_j of an earlier stage j (at most one: j = 2,
+// the array after f^n).  With FP32 or FP64 stage arrays it is taken as
+// (A_ij / A_jj)(fq - f*_j), f*_j = f^n - dt ctn L(f^n), ctn = At_j1 (the first
+// implicit column is 0); with BF16 stage arrays, whose rounding that
+// difference would carry at full weight, as dt A_ij (tau/eps)(Ghat_j - fq)
+// with Ghat_j re-evaluated from the per-cell parameters pq stage j wrote.
 struct StageArgs {
     Geom g;
-    const void *fn;                                        // f^n: base value at the cell
-    const void *fl[2]; double cl[2];                       // transport terms  -dt*cl*L(fl)
-    const void *fq[2]; const double *pq[2]; double cq[2];  // sources +dt*cq*(tau/eps)(Ghat-fq)
+    const void *fn;                    // f^n: base value at the cell
+    const void *fl[2]; double cl[2];   // transport terms  -dt*cl*L(fl)
+    const void *fq[1];                 // state of the implicit term
+    double qa, qd, qb;                 // A_ij, A_jj, b_j of that term
+    double ctn;                        // f*_j = f^n - dt ctn L(f^n)
+    const double *pq;                  // Gaussian parameters of stage j (BF16 stage arrays)
+    double *pout;                      // Gaussian parameters of this stage (GP_N per cell), or null
     int nl, nq;
-    double aii;                                            // implicit coefficient; 0 -> final combination
-    int emit;                                              // write the L1 distance of the result
+    double aii;                        // implicit coefficient; 0 -> final combination
+    int emit;                          // write the L1 distance of the result
     void *fout;
-    // side output of an implicit stage (state type, at least FP32): P = fn - dt sum_l scl[l] L(fl[l])
-    // + dt scq (tau/eps)(Ghat - fq[0]); the final combination reads it as its base
-    void *sout; double scl[2]; double scq;
-    double *pout;                                       // Gaussian parameters (GP_N per cell)
-    double *Uout;                                       // SoA [4][nc]
+    // side output of an implicit stage (state type, at least FP32):
+    //   P' = fn - dt sum_l scl[l] L(fl[l]) + dt b_j Q'_j + sfin (fout - f*_i),
+    // the last term being dt b_i Q'_i of the stage itself; the final
+    // combination reads it as its base
+    void *sout; double scl[2]; double sfin;
+    double *Uout;                      // SoA [4][nc]
     double *l1out;
     const double *eps;
     const int *list;

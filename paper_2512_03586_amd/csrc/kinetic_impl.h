@@ -5,9 +5,14 @@
 // stage_kernel fuses, for every kinetic cell (one L-lane group per cell):
 //   transport L(f^(j)) of earlier stages at every node (upwind or minmod-limited
 //     upwind flux, Sec. 3.2), read straight from the velocity-contiguous f arrays;
-//   the explicit stage sum f* = f^n - dt sum_j At_ij L(f^(j))
-//     + dt sum_j A_ij (tau/eps)(Ghat_j - f^(j)) (eq. RKEI1), where Ghat_j is
-//     re-evaluated from the per-cell parameters stage j stored;
+//   the explicit stage sum f* = f^n - dt sum_j At_ij L(f^(j)) + dt sum_j A_ij Q'_j
+//     (eq. RKEI1).  With FP32 / FP64 stage arrays the implicit term of an
+//     earlier stage j is taken as Q'_j = (f^(j) - f*_j) / (dt A_jj), which
+//     equals (tau/eps)(Ghat_j - f^(j)) for the exact relaxation of stage j,
+//     with f*_j = f^n - dt At_j1 L(f^n) rebuilt from the transport of f^n the
+//     kernel forms anyway (no Gaussian is re-evaluated).  With BF16 stage
+//     arrays that difference would carry their rounding at full weight, so
+//     Ghat_j is re-evaluated from the per-cell parameters stage j stored;
 //   the velocity moments of f* (rho, u, T, Theta; H3 and Sec. 2), with
 //     compensated FP32 sums;
 //   the FP64 closed form of the implicit relaxation,
@@ -15,7 +20,10 @@
 //     Tt = (1-beta) T I + beta Theta, lam = dt A_ii tau/eps,
 //     and the FP64 6x6 discrete-conservation correction of the sampled Gaussian;
 //   f^(i) = (f* + lam Ghat) / (1 + lam), the single write of the stage.
-// The FINAL variant is the final combination (eq. RKEI2): it writes f^{n+1},
+// The last implicit stage of ARS(2,3,3) also writes the partial sum
+//   P' = f^n - dt sum_j bt_j L(f^(j)) + dt sum_j b_j Q'_j   (j = 1 .. 3, L of f^(3) excluded),
+// its own Q'_3 included once f^(3) is known.  The FINAL variant is the final
+// combination (eq. RKEI2) f^{n+1} = P' - dt bt_3 L(f^(3)): it writes f^{n+1},
 // its moments U^{n+1} and the L1 distance to the Maxwellian that the next
 // regime update reads (eq. eqKintoFluid1).
 #pragma once
@@ -538,7 +546,8 @@ __global__ __launch_bounds__((64 * stage_waves<typename Storage<SN>::T, C, FINAL
     constexpr bool INC = increment_storage<SN, SS>();
     static_assert(!INC || std::is_same<SP, T>::value, "increments are taken over state-precision arrays");
     static_assert(!INC || ESBGK_PREFETCH, "increment storage completes stencils in the prefetch buffer");
-    constexpr bool KEEP_P = SIDE && INC;
+    // the side output P is held until the relaxation has added the stage's own Q'
+    constexpr bool KEEP_P = SIDE;
     using Lds = StageLds<T, C, FINAL, KEEP_P>;
     __shared__ Lds lds;
     const Geom &g = a.g;
@@ -551,11 +560,12 @@ __global__ __launch_bounds__((64 * stage_waves<typename Storage<SN>::T, C, FINAL
     const Nbr nb = neighbours(cell, g);
     const T idx = (T)g.idx, idy = (T)g.idy;
     const double te = g.tau / a.eps[cell];
-    const T dt = (T)g.dt, dtte = (T)(g.dt * te);
-
-    GaussEval<T> gq[NQ > 0 ? NQ : 1];
-#pragma unroll
-    for (int q = 0; q < NQ; ++q) gq[q].load(a.pq[q] + (size_t)cell * GP_N);
+    const T dt = (T)g.dt;
+    // implicit term from the stage difference (FP32 / FP64 stage arrays) or
+    // from the re-evaluated Gaussian (BF16 stage arrays)
+    constexpr bool QDIFF = !std::is_same<SS, bf16_t>::value;
+    GaussEval<T> gq;
+    if constexpr (!QDIFF && NQ > 0) gq.load(a.pq + (size_t)cell * GP_N);
 
     // ---- explicit part of the stage, moments on the fly
     MomentAcc<T> macc;
@@ -564,6 +574,7 @@ __global__ __launch_bounds__((64 * stage_waves<typename Storage<SN>::T, C, FINAL
     constexpr int NB = PF ? 2 : 1;
     T base[4], acc[4], qsum[4];  // base: f^n at the cell (final combination: the partial sum P)
     T pacc[4], psum[4];          // side output P of the last implicit stage
+    T fsq[4];                    // f*_j of the stage whose implicit term enters: f^n - dt At_j1 L(f^n)
     // Per-unit work once its transport Lt and centre values cc are known.
     auto unit_body = [&](int m, int l, const Chunk<T> &ch, const T Lt[4], const T cc[4]) {
         const T cl = (T)a.cl[l];
@@ -580,19 +591,36 @@ __global__ __launch_bounds__((64 * stage_waves<typename Storage<SN>::T, C, FINAL
                 if (l == 0) psum[e] = 0;
             }
         }
-        // implicit term of the stage whose state this unit transports
-        constexpr int Q0 = NL - NQ;
-        if (l >= Q0) {
-            const int q = l - Q0 < NQ ? l - Q0 : 0;
-            GaussRow<T> gr;
-            gr.set(gq[q], ch.vy);
-            const T cq = (T)a.cq[q] * dtte;
-            const T sq = SIDE ? (T)a.scq * dtte : (T)0;
+        // implicit term of the stage whose state this unit transports:
+        // dt A_ij Q'_j = (A_ij / A_jj)(f^(j) - f*_j), f*_j formed from L(f^n)
+        static_assert(NQ == 0 || (NQ == 1 && NL == 2), "one implicit term, that of the stage after f^n");
+        if constexpr (NQ > 0 && QDIFF) {
+            if (l == 0) {
+                const T tn = (T)a.ctn;
 #pragma unroll
-            for (int e = 0; e < 4; ++e) {
-                const T hm = gr.hat(gq[q], ch.vx[e]) - cc[e];
-                qsum[e] += cq * hm;
-                if (SIDE) psum[e] += sq * hm;
+                for (int e = 0; e < 4; ++e) fsq[e] = base[e] - dt * (tn * Lt[e]);
+            } else {
+                const T cq = (T)(a.qa / a.qd);
+                const T sq = SIDE ? (T)(a.qb / a.qd) : (T)0;
+#pragma unroll
+                for (int e = 0; e < 4; ++e) {
+                    const T hm = cc[e] - fsq[e];
+                    qsum[e] += cq * hm;
+                    if (SIDE) psum[e] += sq * hm;
+                }
+            }
+        } else if constexpr (NQ > 0) {
+            if (l == 1) {
+                GaussRow<T> gr;
+                gr.set(gq, ch.vy);
+                const T cq = (T)(a.qa * g.dt * te);
+                const T sq = SIDE ? (T)(a.qb * g.dt * te) : (T)0;
+#pragma unroll
+                for (int e = 0; e < 4; ++e) {
+                    const T hm = gr.hat(gq, ch.vx[e]) - cc[e];
+                    qsum[e] += cq * hm;
+                    if (SIDE) psum[e] += sq * hm;
+                }
             }
         }
         if (l == NL - 1) {
@@ -608,11 +636,13 @@ __global__ __launch_bounds__((64 * stage_waves<typename Storage<SN>::T, C, FINAL
                 T pv[4];
 #pragma unroll
                 for (int e = 0; e < 4; ++e) pv[e] = (base[e] - dt * pacc[e]) + psum[e];
+                // held until the relaxation: in LDS, else in the FP32 buffer it is
+                // read back from (the lane reads its own write)
                 if constexpr (Lds::P) {
 #pragma unroll
                     for (int e = 0; e < 4; ++e) lds.p[wave][m][lane][e] = pv[e];
-                } else if constexpr (KEEP_P) {
-                    Storage<SP>::store4((SP *)a.fout + nb.c, (uint32_t)ch.k0, pv);  // read back in the relaxation
+                } else if constexpr (INC) {
+                    Storage<SP>::store4((SP *)a.fout + nb.c, (uint32_t)ch.k0, pv);
                 } else {
                     Storage<SP>::store4((SP *)a.sout + nb.c, (uint32_t)ch.k0, pv);
                 }
@@ -715,25 +745,35 @@ __global__ __launch_bounds__((64 * stage_waves<typename Storage<SN>::T, C, FINAL
         if (g.correction)
             errbits |= correction_coeffs<T, L, C, NV>(lds.g[wave], s, lane, g, ge, Slow, rho, Tm, txx, txy, tyy,
                                                       correction_tol<T>(), dc);
-        const double pref = gp[GP_PREF];
+        if (!QDIFF && a.pout && leader) {
+            // per-cell parameters of the corrected Gaussian, for the next stage's implicit term
+            const double pref = gp[GP_PREF];
+            double *o = a.pout + (size_t)cell * GP_N;
 #pragma unroll
-        for (int q = 0; q < 6; ++q) gp[GP_C0 + q] = pref * ((q == 0 ? 1.0 : 0.0) + dc[q]);
+            for (int q = 0; q < GP_N; ++q)
+                o[q] = (q >= GP_C0 && q < GP_C0 + 6) ? pref * ((q == GP_C0 ? 1.0 : 0.0) + dc[q - GP_C0]) : gp[q];
+        }
 
         // ---- relaxation: f = (f* + lam Gtilde (1 + dc . psi)) / (1 + lam), the stage's single write
         const T d0 = (T)dc[0], d1 = (T)dc[1], d2 = (T)dc[2], d3 = (T)dc[3], d4 = (T)dc[4], d5 = (T)dc[5];
+        // side output: P' = P + dt b_i Q'_i = P + (b_i / A_ii)(f^(i) - f*_i)
+        const T sfin = SIDE ? (T)a.sfin : (T)0;
 #pragma unroll
         for (int m = 0; m < C; ++m) {
             const Chunk<T> ch = chunk_of<T, L, NV>(s, m, g);
             if (ch.active) {
                 const T b = (ch.vy - ge.uy) * ge.ist;
                 const T plin = d1 + d4 * b, pconst = d0 + (d2 + d5 * b) * b;
-                // mixed form: the reference of the stored increment (stage 2: f^n; stage 3: P)
+                // P held from the explicit pass (side output), or the mixed form's
+                // reference of the stored increment of stage 2 (f^n)
                 T rv[4] = {0, 0, 0, 0};
                 if constexpr (Lds::P) {
 #pragma unroll
                     for (int e = 0; e < 4; ++e) rv[e] = lds.p[wave][m][lane][e];
-                } else if constexpr (KEEP_P) {
+                } else if constexpr (KEEP_P && INC) {
                     Storage<SP>::load4((const SP *)a.fout + nb.c, (uint32_t)ch.k0, rv);
+                } else if constexpr (KEEP_P) {
+                    Storage<SP>::load4((const SP *)a.sout + nb.c, (uint32_t)ch.k0, rv);
                 } else if constexpr (INC) {
                     Storage<SN>::load4((const SN *)a.fn + nb.c, (uint32_t)ch.k0, rv);
                 }
@@ -742,13 +782,22 @@ __global__ __launch_bounds__((64 * stage_waves<typename Storage<SN>::T, C, FINAL
                 for (int e = 0; e < 4; ++e) {
                     const T aa = (ch.vx[e] - ge.ux) * ge.ist;
                     const T Ghat = lds.g[wave][m][lane][e] * ((T)1 + ((d3 * aa + plin) * aa + pconst));
-                    fv[e] = (lds.v[wave][m][lane][e] + lamt * Ghat) * inv1;
-                    sv[e] = !INC ? fv[e] : KEEP_P ? rv[e] - fv[e] : fv[e] - rv[e];
+                    const T fs = lds.v[wave][m][lane][e];
+                    fv[e] = (fs + lamt * Ghat) * inv1;
+                    if constexpr (KEEP_P) {
+                        const T pn = rv[e] + sfin * (fv[e] - fs);
+                        sv[e] = INC ? pn - fv[e] : pn;
+                    } else {
+                        sv[e] = INC ? fv[e] - rv[e] : fv[e];
+                    }
                 }
                 if (gc.valid) {
-                    if constexpr (KEEP_P) {
+                    if constexpr (KEEP_P && INC) {
                         Storage<SP>::store4((SP *)a.fout + nb.c, (uint32_t)ch.k0, fv);   // f^(3)
-                        Storage<SS>::store4((SS *)a.sout + nb.c, (uint32_t)ch.k0, sv);   // P - f^(3)
+                        Storage<SS>::store4((SS *)a.sout + nb.c, (uint32_t)ch.k0, sv);   // P' - f^(3)
+                    } else if constexpr (KEEP_P) {
+                        Storage<SS>::store4((SS *)a.fout + nb.c, (uint32_t)ch.k0, fv);   // f^(3)
+                        Storage<SP>::store4((SP *)a.sout + nb.c, (uint32_t)ch.k0, sv);   // P'
                     } else {
                         Storage<SS>::store4((SS *)a.fout + nb.c, (uint32_t)ch.k0, sv);
                     }
@@ -762,11 +811,6 @@ __global__ __launch_bounds__((64 * stage_waves<typename Storage<SN>::T, C, FINAL
                     }
                 }
             }
-        }
-        if (leader) {
-            double *o = a.pout + (size_t)cell * GP_N;
-#pragma unroll
-            for (int q = 0; q < GP_N; ++q) o[q] = gp[q];
         }
     } else {
 #pragma unroll
@@ -974,6 +1018,7 @@ hipError_t launch_stage(const StageArgs &a, int nmax, hipStream_t st) {
     // the kernels take the implicit terms' states from the last NQ transported arrays
     for (int q = 0; q < a.nq; ++q)
         if (a.nl - a.nq + q < 0 || a.fq[q] != a.fl[a.nl - a.nq + q]) return hipErrorInvalidValue;
+    if (a.sout && !(a.aii > 0.0)) return hipErrorInvalidValue;
     if (a.aii > 0.0) {
         if (a.nl < 1 || a.fl[0] != a.fn) return hipErrorInvalidValue;  // implicit stages transport f^n first
         // increment storage: the increment of the second implicit stage is taken over the partial sum
@@ -982,8 +1027,8 @@ hipError_t launch_stage(const StageArgs &a, int nmax, hipStream_t st) {
         if (a.nl == 2 && a.nq == 1 && !a.sout) return stage_dispatch<SN, SS, 2, 1, false, false>(a, nmax, st);
         if (a.nl == 2 && a.nq == 1 && a.sout) return stage_dispatch<SN, SS, 2, 1, false, true>(a, nmax, st);
     } else {
-        // final combination from the partial sum P of the last implicit stage
-        if (a.nl == 1 && a.nq == 1 && !a.sout) return stage_dispatch<SN, SS, 1, 1, true, false>(a, nmax, st);
+        // final combination from the partial sum P' of the last implicit stage
+        if (a.nl == 1 && a.nq == 0) return stage_dispatch<SN, SS, 1, 0, true, false>(a, nmax, st);
     }
     return hipErrorInvalidValue;
 }
