@@ -186,6 +186,71 @@ template <int L, class T> __device__ inline double group_sum_comp(Comp<T> c) {
     }
 }
 
+// Wave-wide totals of six doubles, each lane's six values in, every lane gets
+// all six totals.  A transposed butterfly: the 32-lane halves exchange whole
+// values (v_permlane32_swap: lanes 32-63 of one operand with lanes 0-31 of the
+// other), so after one add the low half holds x[q] and the high half x[q+3];
+// the odd/even 16-lane rows do the same (v_permlane16_swap), then four DPP
+// steps finish inside each row and six readlanes collect the totals.  Each
+// total is one fixed tree over the 64 lanes.
+__device__ inline void swap_halves(double &a, double &b, bool rows16) {
+    const uint64_t ua = (uint64_t)__double_as_longlong(a), ub = (uint64_t)__double_as_longlong(b);
+    uint32_t alo = (uint32_t)ua, ahi = (uint32_t)(ua >> 32), blo = (uint32_t)ub, bhi = (uint32_t)(ub >> 32);
+    if (rows16) {
+        auto lo = __builtin_amdgcn_permlane16_swap(alo, blo, false, false);
+        auto hi = __builtin_amdgcn_permlane16_swap(ahi, bhi, false, false);
+        alo = lo[0]; blo = lo[1]; ahi = hi[0]; bhi = hi[1];
+    } else {
+        auto lo = __builtin_amdgcn_permlane32_swap(alo, blo, false, false);
+        auto hi = __builtin_amdgcn_permlane32_swap(ahi, bhi, false, false);
+        alo = lo[0]; blo = lo[1]; ahi = hi[0]; bhi = hi[1];
+    }
+    a = __longlong_as_double((long long)(((uint64_t)ahi << 32) | alo));
+    b = __longlong_as_double((long long)(((uint64_t)bhi << 32) | blo));
+}
+
+__device__ inline double row_sum(double v) {
+    v += partner<0>(v);
+    v += partner<1>(v);
+    v += partner<2>(v);
+    v += partner<3>(v);
+    return v;
+}
+
+__device__ inline void wave_sum6(double x[6]) {
+    double y[3];
+#pragma unroll
+    for (int q = 0; q < 3; ++q) {
+        double a = x[q], b = x[q + 3];
+        swap_halves(a, b, false);
+        y[q] = a + b;  // lanes 0-31: x[q] over lanes l, l+32; lanes 32-63: x[q+3]
+    }
+    double a = y[0], b = y[1];
+    swap_halves(a, b, true);
+    double z0 = row_sum(a + b);  // rows 0, 1, 2, 3: x0, x1, x3, x4
+    a = y[2]; b = y[2];
+    swap_halves(a, b, true);
+    double z1 = row_sum(a + b);  // rows 0, 1: x2; rows 2, 3: x5
+    x[0] = readlane(z0, 0);
+    x[1] = readlane(z0, 16);
+    x[3] = readlane(z0, 32);
+    x[4] = readlane(z0, 48);
+    x[2] = readlane(z1, 0);
+    x[5] = readlane(z1, 32);
+}
+
+// Group totals of six compensated lane partials (see group_sum_comp).
+template <int L, class T> __device__ inline void group_sum_comp6(const Comp<T> c[6], double out[6]) {
+    if constexpr (L == 64 && ESBGK_COMP_BUTTERFLY == 0) {
+#pragma unroll
+        for (int q = 0; q < 6; ++q) out[q] = (double)c[q].hi + (double)c[q].lo;
+        wave_sum6(out);
+    } else {
+#pragma unroll
+        for (int q = 0; q < 6; ++q) out[q] = group_sum_comp<L>(c[q]);
+    }
+}
+
 // -------------------------------------------------------- kernel geometry
 
 struct Geom {

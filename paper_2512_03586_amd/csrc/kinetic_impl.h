@@ -277,8 +277,9 @@ __device__ inline void group_moments(const T v[C][4], int s, const Geom &g, doub
         }
     }
     double M[6];
+    group_sum_comp6<L>(cs, M);
 #pragma unroll
-    for (int q = 0; q < 6; ++q) M[q] = g.w * group_sum_comp<L>(cs[q]);
+    for (int q = 0; q < 6; ++q) M[q] *= g.w;
     const double rho = M[0];
     const double irho = 1.0 / rho;
     const double ux = M[1] * irho, uy = M[2] * irho;
@@ -343,8 +344,9 @@ template <class T> struct MomentAcc {
     template <int L> __device__ inline void finish(double w, double out[7]) {
         fold();
         double M[6];
+        group_sum_comp6<L>(cs, M);
 #pragma unroll
-        for (int q = 0; q < 6; ++q) M[q] = w * group_sum_comp<L>(cs[q]);
+        for (int q = 0; q < 6; ++q) M[q] *= w;
         const double rho = M[0];
         const double irho = 1.0 / rho;
         const double ux = M[1] * irho, uy = M[2] * irho;
@@ -374,8 +376,11 @@ template <class T, int C> __host__ __device__ constexpr int waves_per_block() {
 // 80 KB (nv <= 32), else in the FP32 buffer f^(3) is written to (the wave
 // reads back its own write, from L2).  Four waves per block when the block's
 // LDS stays within 80 KB, else one.
+#ifndef ESBGK_P_LDS
+#define ESBGK_P_LDS 1
+#endif
 template <class T, int C> __host__ __device__ constexpr bool p_in_lds() {
-    return 4 * 3 * C * 64 * 4 * (int)sizeof(T) <= 80 * 1024;
+    return ESBGK_P_LDS && 4 * 3 * C * 64 * 4 * (int)sizeof(T) <= 80 * 1024;
 }
 template <class T, int C, bool FINAL, bool KEEP_P> __host__ __device__ constexpr int stage_waves() {
     return 4 * (FINAL ? 1 : (KEEP_P && p_in_lds<T, C>()) ? 3 : 2) * C * 64 * 4 * (int)sizeof(T) <= 80 * 1024 ? 4
@@ -492,8 +497,9 @@ __device__ inline void gaussian_pass(T (&glds)[C][64][4], T (*vlds)[64][4], int 
             for (int q = 0; q < 6; ++q) { lowc[q].add(low[q]); low[q] = 0; }
         }
     }
+    group_sum_comp6<L>(lowc, Slow);
 #pragma unroll
-    for (int q = 0; q < 6; ++q) Slow[q] = g.w * group_sum_comp<L>(lowc[q]);
+    for (int q = 0; q < 6; ++q) Slow[q] *= g.w;
 }
 
 // Tolerance on |r|/rho for the closed-form correction: its residual is about
