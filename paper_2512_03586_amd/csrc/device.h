@@ -398,6 +398,9 @@ template <class T> struct GaussRow {
         const T ex = vx - g.ux;
         return fast_exp2((g.qxx * ex + qy_lin) * ex + qy_const);
     }
+    // the sampled Gaussian pref exp2(Q): one expression wherever it is formed,
+    // so a value evaluated again equals the one staged
+    __device__ inline T sampled(const GaussEval<T> &g, T pref, T vx) const { return pref * tilde(g, vx); }
     __device__ inline T hat(const GaussEval<T> &g, T vx) const {
         const T ex = vx - g.ux;
         const T a = ex * g.ist;

@@ -370,21 +370,28 @@ template <class T, int C> __host__ __device__ constexpr int waves_per_block() {
     return 4 * (2 * C * 64 * 4 * (int)sizeof(T)) <= 80 * 1024 ? 4 : 1;
 }
 
-// Stage kernels: the implicit stages stage f* and the sampled Gaussian, the
-// final combination f* only.  The mixed form's last implicit stage also keeps
-// P until f^(3) is known: in LDS while three arrays of four waves fit in
-// 80 KB (nv <= 32), else in the FP32 buffer f^(3) is written to (the wave
-// reads back its own write, from L2).  Four waves per block when the block's
-// LDS stays within 80 KB, else one.
+// Stage kernels: the implicit stages stage f* in LDS (the final combination
+// too), and the sampled Gaussian when ESBGK_G_LDS is set (else the relaxation
+// evaluates it again, identically).  The last implicit stage of ARS(2,3,3)
+// also keeps P until f^(3) is known: in LDS while the block's arrays fit in
+// 80 KB, else in an FP32 buffer it writes and reads back (the lane reads its
+// own write, from L2).  Four waves per block when the block's LDS stays within
+// 80 KB, else one.
 #ifndef ESBGK_P_LDS
 #define ESBGK_P_LDS 1
 #endif
+#ifndef ESBGK_G_LDS
+#define ESBGK_G_LDS 1
+#endif
 template <class T, int C> __host__ __device__ constexpr bool p_in_lds() {
-    return ESBGK_P_LDS && 4 * 3 * C * 64 * 4 * (int)sizeof(T) <= 80 * 1024;
+    return ESBGK_P_LDS && 4 * (2 + ESBGK_G_LDS) * C * 64 * 4 * (int)sizeof(T) <= 80 * 1024;
 }
 template <class T, int C, bool FINAL, bool KEEP_P> __host__ __device__ constexpr int stage_waves() {
-    return 4 * (FINAL ? 1 : (KEEP_P && p_in_lds<T, C>()) ? 3 : 2) * C * 64 * 4 * (int)sizeof(T) <= 80 * 1024 ? 4
-                                                                                                           : 1;
+    return 4 * (1 + (FINAL ? 0 : ESBGK_G_LDS) + ((KEEP_P && p_in_lds<T, C>()) ? 1 : 0)) * C * 64 * 4 *
+                       (int)sizeof(T) <=
+                   80 * 1024
+               ? 4
+               : 1;
 }
 
 // Optional LDS arrays, as (possibly empty) bases so that an absent one takes no space.
@@ -394,7 +401,7 @@ template <class T, int W, int C, bool ON> struct LdsPartial { T p[W][C][64][4]; 
 template <class T, int W, int C> struct LdsPartial<T, W, C, false> {};
 
 template <class T, int C, bool FINAL, bool KEEP_P>
-struct StageLds : LdsGauss<T, stage_waves<T, C, FINAL, KEEP_P>(), C, !FINAL>,
+struct StageLds : LdsGauss<T, stage_waves<T, C, FINAL, KEEP_P>(), C, !FINAL && ESBGK_G_LDS>,
                   LdsPartial<T, stage_waves<T, C, FINAL, KEEP_P>(), C, KEEP_P && p_in_lds<T, C>()> {
     static constexpr int W = stage_waves<T, C, FINAL, KEEP_P>();
     static constexpr bool P = KEEP_P && p_in_lds<T, C>();
@@ -413,9 +420,10 @@ struct StageLds : LdsGauss<T, stage_waves<T, C, FINAL, KEEP_P>(), C, !FINAL>,
 // the quadrature error); otherwise the nine higher discrete moments are summed
 // from LDS and the exact discrete Gram matrix is solved.  Returns error bits.
 template <class T, int L, int C, int NV>
-__device__ inline int correction_coeffs(const T (&glds)[C][64][4], int s, int lane, const Geom &g,
-                                        const GaussEval<T> &ge, const double Slow[6], double rho, double Tm,
-                                        double txx, double txy, double tyy, double tol, double dc[6]) {
+__device__ inline int correction_coeffs(const T (*glds)[64][4], int s, int lane, const Geom &g,
+                                        const GaussEval<T> &ge, T pref, const double Slow[6], double rho,
+                                        double Tm, double txx, double txy, double tyy, double tol,
+                                        double dc[6]) {
     const double iT = 1.0 / Tm;
     double r[6];
     r[0] = rho - Slow[0];
@@ -435,17 +443,20 @@ __device__ inline int correction_coeffs(const T (&glds)[C][64][4], int s, int la
         solve_correction_gaussian(rr, txx * iT, txy * iT, tyy * iT, dc);
         return 0;
     }
-    // exact path: moments of order 3 and 4 of the stored Gaussian
+    // exact path: moments of order 3 and 4 of the sampled Gaussian (staged in
+    // glds, or evaluated again)
     T high[9] = {0, 0, 0, 0, 0, 0, 0, 0, 0};
 #pragma unroll
     for (int m = 0; m < C; ++m) {
         const Chunk<T> ch = chunk_of<T, L, NV>(s, m, g);
         if (ch.active) {
             const T b = (ch.vy - ge.uy) * ge.ist;
+            GaussRow<T> gr;
+            if (!glds) gr.set(ge, ch.vy);
             T p[5] = {0, 0, 0, 0, 0};
 #pragma unroll
             for (int e = 0; e < 4; ++e) {
-                const T G = glds[m][lane][e];
+                const T G = glds ? glds[m][lane][e] : gr.sampled(ge, pref, ch.vx[e]);
                 const T a = (ch.vx[e] - ge.ux) * ge.ist;
                 const T Ga = G * a, Ga2 = Ga * a, Ga3 = Ga2 * a;
                 p[0] += G; p[1] += Ga; p[2] += Ga2; p[3] += Ga3; p[4] += Ga3 * a;
@@ -465,10 +476,10 @@ __device__ inline int correction_coeffs(const T (&glds)[C][64][4], int s, int la
 }
 
 // Pass 1 over the nodes for the Gaussian with parameters ge (prefactor pref):
-// Gtilde into glds, the six compensated discrete moments of order <= 2 into
-// Slow, and (when vlds is given) v <- (v + lam Gtilde) * inv1 in place.
+// Gtilde into glds (when given), the six compensated discrete moments of order
+// <= 2 into Slow, and (when vlds is given) v <- (v + lam Gtilde) * inv1 in place.
 template <class T, int L, int C, int NV>
-__device__ inline void gaussian_pass(T (&glds)[C][64][4], T (*vlds)[64][4], int s, int lane, const Geom &g,
+__device__ inline void gaussian_pass(T (*glds)[64][4], T (*vlds)[64][4], int s, int lane, const Geom &g,
                                      const GaussEval<T> &ge, T pref, T lam, T inv1, double Slow[6]) {
     Comp<T> lowc[6];
     T low[6] = {0, 0, 0, 0, 0, 0};
@@ -482,11 +493,11 @@ __device__ inline void gaussian_pass(T (&glds)[C][64][4], T (*vlds)[64][4], int 
             T p0 = 0, p1 = 0, p2 = 0;
 #pragma unroll
             for (int e = 0; e < 4; ++e) {
-                const T G = pref * gr.tilde(ge, ch.vx[e]);
+                const T G = gr.sampled(ge, pref, ch.vx[e]);
                 const T a = (ch.vx[e] - ge.ux) * ge.ist;
                 const T Ga = G * a;
                 p0 += G; p1 += Ga; p2 += Ga * a;
-                glds[m][lane][e] = G;
+                if (glds) glds[m][lane][e] = G;
                 if (vlds) vlds[m][lane][e] = (vlds[m][lane][e] + lam * G) * inv1;
             }
             low[0] += p0; low[1] += p1; low[2] += b * p0;
@@ -746,10 +757,13 @@ __global__ __launch_bounds__((64 * stage_waves<typename Storage<SN>::T, C, FINAL
         const T lamt = (T)lam, inv1 = (T)(1.0 / (1.0 + lam));
         // ---- Gaussian pass: Gtilde into LDS and its low-order discrete moments
         double Slow[6];
-        gaussian_pass<T, L, C, NV>(lds.g[wave], nullptr, s, lane, g, ge, (T)gp[GP_PREF], lamt, inv1, Slow);
+        T(*gl)[64][4] = nullptr;
+        if constexpr (ESBGK_G_LDS) gl = lds.g[wave];
+        const T prefg = (T)gp[GP_PREF];
+        gaussian_pass<T, L, C, NV>(gl, nullptr, s, lane, g, ge, prefg, lamt, inv1, Slow);
         double dc[6] = {0, 0, 0, 0, 0, 0};
         if (g.correction)
-            errbits |= correction_coeffs<T, L, C, NV>(lds.g[wave], s, lane, g, ge, Slow, rho, Tm, txx, txy, tyy,
+            errbits |= correction_coeffs<T, L, C, NV>(gl, s, lane, g, ge, prefg, Slow, rho, Tm, txx, txy, tyy,
                                                       correction_tol<T>(), dc);
         if (!QDIFF && a.pout && leader) {
             // per-cell parameters of the corrected Gaussian, for the next stage's implicit term
@@ -770,6 +784,8 @@ __global__ __launch_bounds__((64 * stage_waves<typename Storage<SN>::T, C, FINAL
             if (ch.active) {
                 const T b = (ch.vy - ge.uy) * ge.ist;
                 const T plin = d1 + d4 * b, pconst = d0 + (d2 + d5 * b) * b;
+                GaussRow<T> gr;
+                if (!ESBGK_G_LDS) gr.set(ge, ch.vy);
                 // P held from the explicit pass (side output), or the mixed form's
                 // reference of the stored increment of stage 2 (f^n)
                 T rv[4] = {0, 0, 0, 0};
@@ -787,7 +803,10 @@ __global__ __launch_bounds__((64 * stage_waves<typename Storage<SN>::T, C, FINAL
 #pragma unroll
                 for (int e = 0; e < 4; ++e) {
                     const T aa = (ch.vx[e] - ge.ux) * ge.ist;
-                    const T Ghat = lds.g[wave][m][lane][e] * ((T)1 + ((d3 * aa + plin) * aa + pconst));
+                    T Gt;
+                    if constexpr (ESBGK_G_LDS) Gt = lds.g[wave][m][lane][e];
+                    else Gt = gr.sampled(ge, prefg, ch.vx[e]);
+                    const T Ghat = Gt * ((T)1 + ((d3 * aa + plin) * aa + pconst));
                     const T fs = lds.v[wave][m][lane][e];
                     fv[e] = (fs + lamt * Ghat) * inv1;
                     if constexpr (KEEP_P) {
@@ -874,8 +893,8 @@ __global__ __launch_bounds__((64 * waves_per_block<typename Storage<S>::T, C>())
     gaussian_pass<T, L, C, NV>(glds[wave], nullptr, s, lane, g, ge, (T)gp[GP_PREF], (T)0, (T)1, Slow);
     double dc[6] = {0, 0, 0, 0, 0, 0};
     if (g.correction)
-        errbits |= correction_coeffs<T, L, C, NV>(glds[wave], s, lane, g, ge, Slow, rho, Tm, Tm, 0.0, Tm,
-                                                  correction_tol<T>(), dc);
+        errbits |= correction_coeffs<T, L, C, NV>(glds[wave], s, lane, g, ge, (T)gp[GP_PREF], Slow, rho, Tm, Tm,
+                                                  0.0, Tm, correction_tol<T>(), dc);
     const T d0 = (T)dc[0], d1 = (T)dc[1], d2 = (T)dc[2], d3 = (T)dc[3], d4 = (T)dc[4], d5 = (T)dc[5];
 #pragma unroll
     for (int m = 0; m < C; ++m) {
