@@ -103,7 +103,89 @@ def parse():
     ap.add_argument("--calibrate-copy", type=int, default=0, metavar="MIB",
                     help="first run one plain device-to-device tensor copy of MIB MiB (a kernel of "
                          "known traffic, to scale HBM byte counters)")
+    ap.add_argument("--record-traffic", nargs=3, metavar=("STATS_CSV", "FETCH_CSV", "WRITE_CSV"),
+                    help="no GPU: summarize rocprofv3 output of this same bench command (--kernel-trace "
+                         "--stats, then --pmc FETCH_SIZE, then --pmc WRITE_SIZE, each with "
+                         "--calibrate-copy) as a markdown table, and for the default FP32 workload write "
+                         "the per-launch HBM bytes of the stage kernels to profiles/traffic.json")
     return ap.parse_args()
+
+
+def stage_class(name):
+    """stage2 / stage3 / final for a stage_kernel<SN, SS, NV, L, C, NL, NQ, FINAL, RECON, SIDE>
+    dispatch name, else None."""
+    if "stage_kernel<" not in name:
+        return None
+    t = [x.strip() for x in name.split("stage_kernel<", 1)[1].split(">", 1)[0].split(",")]
+    nl, final = int(t[5]), t[7] == "true"
+    return "final" if final else ("stage3" if nl == 2 else "stage2")
+
+
+def record_traffic(args):
+    """Per-launch HBM bytes from rocprofv3 FETCH_SIZE / WRITE_SIZE (KiB per
+    dispatch), scaled by what the same counters read for the calibration copy,
+    over the timed dispatches of each stage kernel (the last `steps` ones)."""
+    import csv
+    stats_csv, fetch_csv, write_csv = args.record_traffic
+    wl = WORKLOADS[args.workload]
+    steps = args.steps if args.steps > 0 else wl["steps"]
+    mib = args.calibrate_copy
+    if mib <= 0:
+        sys.exit("--record-traffic needs the --calibrate-copy MIB of the profiled command")
+
+    def counters(path):
+        rows = sorted(csv.DictReader(open(path)), key=lambda r: int(r["Dispatch_Id"]))
+        copies = [float(r["Counter_Value"]) for r in rows if "copyBuffer" in r["Kernel_Name"]]
+        factor = mib * 1024.0 / max(copies)  # KiB the copy must move / KiB counted
+        per = {}
+        for r in rows:
+            per.setdefault(r["Kernel_Name"], []).append(float(r["Counter_Value"]) * 1024.0 * factor)
+        return factor, per
+
+    ff, fetch = counters(fetch_csv)
+    wf, write = counters(write_csv)
+    stats = list(csv.DictReader(open(stats_csv)))
+    print(f"Calibration: FETCH_SIZE x {ff:.3f}, WRITE_SIZE x {wf:.3f} (the {mib} MiB device copy)\n")
+    print("| Kernel | Calls | Avg us | Min us | Max us | Share | FETCH MB/launch | WRITE MB/launch |")
+    print("|---|---|---|---|---|---|---|---|")
+    for r in stats:
+        n = r["Name"]
+        short = n.replace("void ", "").replace("esbgk::", "").split("(")[0]
+        fm = sum(fetch.get(n, [0])) / max(len(fetch.get(n, [1])), 1) / 1e6
+        wm = sum(write.get(n, [0])) / max(len(write.get(n, [1])), 1) / 1e6
+        print(f"| `{short[:90]}` | {r['Calls']} | {float(r['AverageNs']) / 1e3:.2f} | {float(r['MinNs']) / 1e3:.2f} "
+              f"| {float(r['MaxNs']) / 1e3:.2f} | {float(r['Percentage']):.1f}% | {fm:.1f} | {wm:.1f} |")
+    rec = {"command": "python -u bench.py --no-cpu-baseline"
+                      + (f" --precision {args.precision}" if args.precision != "fp32" else "")
+                      + (f" --workload {args.workload}" if args.workload != "riemann4" else "")
+                      + f" --calibrate-copy {mib}",
+           "workload": args.workload, "precision": args.precision, "steps": steps,
+           "source_sha256": kernel_source_digest(), "fetch_factor": ff, "write_factor": wf, "kernels": {},
+           "sources": "device.h, kernels.h, kinetic_impl.h, kinetic_*.hip"}
+    # durations of the timed dispatches from the kernel trace beside the stats file
+    trace_csv = os.path.join(os.path.dirname(stats_csv), os.path.basename(stats_csv).replace("kernel_stats",
+                                                                                            "kernel_trace"))
+    dur = {}
+    for r in sorted(csv.DictReader(open(trace_csv)), key=lambda r: int(r["Dispatch_Id"])):
+        c = stage_class(r["Kernel_Name"])
+        if c:
+            dur.setdefault(c, []).append((int(r["End_Timestamp"]) - int(r["Start_Timestamp"])) * 1e-3)
+    print(f"\nTimed dispatches (the last {steps} of each stage kernel): average duration and HBM MB per launch\n")
+    print("| Kernel | avg us (trace) | FETCH MB | WRITE MB | total MB |")
+    print("|---|---|---|---|---|")
+    for cls in ("stage2", "stage3", "final"):
+        fs = [v for n, vs in fetch.items() if stage_class(n) == cls for v in vs][-steps:]
+        ws = [v for n, vs in write.items() if stage_class(n) == cls for v in vs][-steps:]
+        ds = dur.get(cls, [])[-steps:]
+        if not fs or not ws:
+            continue
+        f, w = sum(fs) / len(fs), sum(ws) / len(ws)
+        rec["kernels"][cls] = {"fetch_bytes_per_launch": f, "write_bytes_per_launch": w}
+        print(f"| {cls} | {sum(ds) / max(len(ds), 1):.1f} | {f / 1e6:.1f} | {w / 1e6:.1f} | {(f + w) / 1e6:.1f} |")
+    if args.precision == "fp32" and args.workload == "riemann4":
+        with open(TRAFFIC_FILE, "w") as fh:
+            json.dump(rec, fh, indent=1)
+            fh.write("\n")
 
 
 def cpu_baseline(wl, nsteps):
@@ -138,6 +220,9 @@ def cpu_baseline(wl, nsteps):
 
 def main():
     args = parse()
+    if args.record_traffic:
+        record_traffic(args)
+        return
     if args.gpus != 1:
         print(f"bench.py measures one GPU only (got --gpus {args.gpus}); the multi-GPU path is a "
               f"design, not built in this project", file=sys.stderr)

@@ -44,6 +44,8 @@ size_t align256(size_t x) { return (x + 255) & ~(size_t)255; }
 // bytes per value of the state arrays (f^n) and of the stage arrays (f^(2), f^(3))
 size_t state_elem(int precision) { return precision == ESBGK_FP64 ? 8 : precision == ESBGK_BF16 ? 2 : 4; }
 size_t stage_elem(int precision) { return precision == ESBGK_FP64 ? 8 : precision == ESBGK_FP32 ? 4 : 2; }
+// whether stage 3 re-evaluates stage 2's Gaussian (and so needs its parameters)
+bool stage_gauss_params(int precision) { return stage_elem(precision) == 2 || !ESBGK_QDIFF; }
 
 // IMEX tableaux, 3 stages (Sec. 3.4.2 for ARS(2,3,3); ARS(2,2,2) its
 // second-order sibling).  Explicit (At, bt), implicit (A, b).
@@ -109,7 +111,7 @@ Layout layout(const esbgk_config *c) {
     L.fP = take(c->scheme == ESBGK_ARS233 ? nc * nv2 * std::max<size_t>(4, state_elem(c->precision)) : 0);
     for (int q = 0; q < 4; ++q) L.U[q] = take(4 * nc * sizeof(double));
     // Gaussian parameters of stage 2, read by stage 3 when the stage arrays are BF16
-    L.gp = take(stage_elem(c->precision) == 2 ? (size_t)GP_N * nc * sizeof(double) : 0);
+    L.gp = take(stage_gauss_params(c->precision) ? (size_t)GP_N * nc * sizeof(double) : 0);
     L.eps = take(nc * sizeof(double));
     L.l1 = take(nc * sizeof(double));
     L.prim = take(4 * nc * sizeof(double));
@@ -476,7 +478,7 @@ int esbgk_create(const esbgk_config *cfg, void *d_workspace, size_t bytes, esbgk
     for (int q = 0; q < 3; ++q) c->f[q] = w + L.f[q];
     c->fP = w + L.fP;
     for (int q = 0; q < 4; ++q) c->U[q] = (double *)(w + L.U[q]);
-    c->gp = stage_elem(cfg->precision) == 2 ? (double *)(w + L.gp) : nullptr;
+    c->gp = stage_gauss_params(cfg->precision) ? (double *)(w + L.gp) : nullptr;
     c->eps = (double *)(w + L.eps);
     c->l1 = (double *)(w + L.l1);
     c->prim = (double *)(w + L.prim);

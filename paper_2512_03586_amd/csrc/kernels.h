@@ -1,6 +1,8 @@
 // kernels.h -- argument blocks and host launchers of the engine's kernels.
 #pragma once
 
+#include <type_traits>
+
 #include "device.h"
 
 namespace esbgk {
@@ -18,6 +20,15 @@ namespace esbgk {
 // implicit column is 0); with BF16 stage arrays, whose rounding that
 // difference would carry at full weight, as dt A_ij (tau/eps)(Ghat_j - fq)
 // with Ghat_j re-evaluated from the per-cell parameters pq stage j wrote.
+// 1: FP32 / FP64 stage arrays take the implicit term from the stage
+// difference; 0: every form re-evaluates the Gaussian (as the BF16 forms do)
+#ifndef ESBGK_QDIFF
+#define ESBGK_QDIFF 1
+#endif
+template <class SS> __host__ __device__ constexpr bool qdiff_form() {
+    return ESBGK_QDIFF && !std::is_same<SS, bf16_t>::value;
+}
+
 struct StageArgs {
     Geom g;
     const void *fn;                    // f^n: base value at the cell

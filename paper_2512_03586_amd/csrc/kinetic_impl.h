@@ -370,28 +370,39 @@ template <class T, int C> __host__ __device__ constexpr int waves_per_block() {
     return 4 * (2 * C * 64 * 4 * (int)sizeof(T)) <= 80 * 1024 ? 4 : 1;
 }
 
-// Stage kernels: the implicit stages stage f* in LDS (the final combination
-// too), and the sampled Gaussian when ESBGK_G_LDS is set (else the relaxation
-// evaluates it again, identically).  The last implicit stage of ARS(2,3,3)
-// also keeps P until f^(3) is known: in LDS while the block's arrays fit in
-// 80 KB, else in an FP32 buffer it writes and reads back (the lane reads its
-// own write, from L2).  Four waves per block when the block's LDS stays within
-// 80 KB, else one.
+// LDS of the stage kernels, per wave, in arrays of C x 64 x 4 values: f*
+// (always); the sampled Gaussian of an implicit stage while the kernel's
+// arrays for four waves fit in 80 KB (stage 2 up to nv = 48, the last stage of
+// ARS(2,3,3) up to nv = 32, in FP32), else the relaxation evaluates it again,
+// identically; and, in the last implicit stage of ARS(2,3,3), P until f^(3) is
+// known, when it fits beside the others (else it goes to an FP32 buffer it is
+// read back from; the lane reads its own write, from L2).  Four waves per
+// block when the block's LDS stays within 80 KB, else one.  (Measured: at
+// nv = 64 re-evaluating the Gaussian at higher occupancy is 18% faster than
+// staging it; at nv = 48 staging is faster for stage 2, re-evaluating with P in
+// LDS faster for the last stage.)
 #ifndef ESBGK_P_LDS
 #define ESBGK_P_LDS 1
 #endif
 #ifndef ESBGK_G_LDS
 #define ESBGK_G_LDS 1
 #endif
+template <class T, int C> __host__ __device__ constexpr int lds_array_bytes() {
+    return C * 64 * 4 * (int)sizeof(T);
+}
+template <class T, int C, bool KEEP_P> __host__ __device__ constexpr bool g_in_lds() {
+    return ESBGK_G_LDS && 4 * (KEEP_P ? 3 : 2) * lds_array_bytes<T, C>() <= 80 * 1024;
+}
 template <class T, int C> __host__ __device__ constexpr bool p_in_lds() {
-    return ESBGK_P_LDS && 4 * (2 + ESBGK_G_LDS) * C * 64 * 4 * (int)sizeof(T) <= 80 * 1024;
+    return ESBGK_P_LDS && (2 + (g_in_lds<T, C, true>() ? 1 : 0)) * lds_array_bytes<T, C>() <= 80 * 1024;
+}
+// the side output P is held until the relaxation has added the stage's own Q'
+template <bool SIDE> __host__ __device__ constexpr bool keep_p() { return SIDE; }
+template <class T, int C, bool FINAL, bool KEEP_P> __host__ __device__ constexpr int stage_arrays() {
+    return 1 + ((!FINAL && g_in_lds<T, C, KEEP_P>()) ? 1 : 0) + ((KEEP_P && p_in_lds<T, C>()) ? 1 : 0);
 }
 template <class T, int C, bool FINAL, bool KEEP_P> __host__ __device__ constexpr int stage_waves() {
-    return 4 * (1 + (FINAL ? 0 : ESBGK_G_LDS) + ((KEEP_P && p_in_lds<T, C>()) ? 1 : 0)) * C * 64 * 4 *
-                       (int)sizeof(T) <=
-                   80 * 1024
-               ? 4
-               : 1;
+    return 4 * stage_arrays<T, C, FINAL, KEEP_P>() * lds_array_bytes<T, C>() <= 80 * 1024 ? 4 : 1;
 }
 
 // Optional LDS arrays, as (possibly empty) bases so that an absent one takes no space.
@@ -401,10 +412,11 @@ template <class T, int W, int C, bool ON> struct LdsPartial { T p[W][C][64][4]; 
 template <class T, int W, int C> struct LdsPartial<T, W, C, false> {};
 
 template <class T, int C, bool FINAL, bool KEEP_P>
-struct StageLds : LdsGauss<T, stage_waves<T, C, FINAL, KEEP_P>(), C, !FINAL && ESBGK_G_LDS>,
+struct StageLds : LdsGauss<T, stage_waves<T, C, FINAL, KEEP_P>(), C, !FINAL && g_in_lds<T, C, KEEP_P>()>,
                   LdsPartial<T, stage_waves<T, C, FINAL, KEEP_P>(), C, KEEP_P && p_in_lds<T, C>()> {
     static constexpr int W = stage_waves<T, C, FINAL, KEEP_P>();
     static constexpr bool P = KEEP_P && p_in_lds<T, C>();
+    static constexpr bool G = !FINAL && g_in_lds<T, C, KEEP_P>();
     T v[W][C][64][4];  // [wave in block][chunk][lane][node]: f*
 };
 
@@ -553,8 +565,7 @@ template <class T, int RECON> __device__ inline void add_stencil(Stencil<T> &dst
 }
 
 template <class SN, class SS, int NV, int L, int C, int NL, int NQ, bool FINAL, int RECON, bool SIDE>
-__global__ __launch_bounds__((64 * stage_waves<typename Storage<SN>::T, C, FINAL,
-                                                (SIDE && increment_storage<SN, SS>())>()),
+__global__ __launch_bounds__((64 * stage_waves<typename Storage<SN>::T, C, FINAL, keep_p<SIDE>()>()),
                              (FINAL ? ESBGK_FINAL_MIN_WAVES : ESBGK_STAGE_MIN_WAVES)) void stage_kernel(
     StageArgs a) {
     using T = typename Storage<SN>::T;
@@ -563,8 +574,7 @@ __global__ __launch_bounds__((64 * stage_waves<typename Storage<SN>::T, C, FINAL
     constexpr bool INC = increment_storage<SN, SS>();
     static_assert(!INC || std::is_same<SP, T>::value, "increments are taken over state-precision arrays");
     static_assert(!INC || ESBGK_PREFETCH, "increment storage completes stencils in the prefetch buffer");
-    // the side output P is held until the relaxation has added the stage's own Q'
-    constexpr bool KEEP_P = SIDE;
+    constexpr bool KEEP_P = keep_p<SIDE>();
     using Lds = StageLds<T, C, FINAL, KEEP_P>;
     __shared__ Lds lds;
     const Geom &g = a.g;
@@ -580,7 +590,7 @@ __global__ __launch_bounds__((64 * stage_waves<typename Storage<SN>::T, C, FINAL
     const T dt = (T)g.dt;
     // implicit term from the stage difference (FP32 / FP64 stage arrays) or
     // from the re-evaluated Gaussian (BF16 stage arrays)
-    constexpr bool QDIFF = !std::is_same<SS, bf16_t>::value;
+    constexpr bool QDIFF = qdiff_form<SS>();
     GaussEval<T> gq;
     if constexpr (!QDIFF && NQ > 0) gq.load(a.pq + (size_t)cell * GP_N);
 
@@ -758,7 +768,7 @@ __global__ __launch_bounds__((64 * stage_waves<typename Storage<SN>::T, C, FINAL
         // ---- Gaussian pass: Gtilde into LDS and its low-order discrete moments
         double Slow[6];
         T(*gl)[64][4] = nullptr;
-        if constexpr (ESBGK_G_LDS) gl = lds.g[wave];
+        if constexpr (Lds::G) gl = lds.g[wave];
         const T prefg = (T)gp[GP_PREF];
         gaussian_pass<T, L, C, NV>(gl, nullptr, s, lane, g, ge, prefg, lamt, inv1, Slow);
         double dc[6] = {0, 0, 0, 0, 0, 0};
@@ -785,7 +795,7 @@ __global__ __launch_bounds__((64 * stage_waves<typename Storage<SN>::T, C, FINAL
                 const T b = (ch.vy - ge.uy) * ge.ist;
                 const T plin = d1 + d4 * b, pconst = d0 + (d2 + d5 * b) * b;
                 GaussRow<T> gr;
-                if (!ESBGK_G_LDS) gr.set(ge, ch.vy);
+                if (!Lds::G) gr.set(ge, ch.vy);
                 // P held from the explicit pass (side output), or the mixed form's
                 // reference of the stored increment of stage 2 (f^n)
                 T rv[4] = {0, 0, 0, 0};
@@ -804,7 +814,7 @@ __global__ __launch_bounds__((64 * stage_waves<typename Storage<SN>::T, C, FINAL
                 for (int e = 0; e < 4; ++e) {
                     const T aa = (ch.vx[e] - ge.ux) * ge.ist;
                     T Gt;
-                    if constexpr (ESBGK_G_LDS) Gt = lds.g[wave][m][lane][e];
+                    if constexpr (Lds::G) Gt = lds.g[wave][m][lane][e];
                     else Gt = gr.sampled(ge, prefg, ch.vx[e]);
                     const T Ghat = Gt * ((T)1 + ((d3 * aa + plin) * aa + pconst));
                     const T fs = lds.v[wave][m][lane][e];
@@ -1023,8 +1033,7 @@ static hipError_t stage_dispatch(const StageArgs &a, int nmax, hipStream_t st) {
     const Shape sh = shape_for(a.g.nv2);
 #define ESBGK_CASE(NN, LL, CC)                                                                                     \
     if ((NN == 0) ? (sh.L == LL && sh.C == CC) : (a.g.nv == NN)) {                                                    \
-        constexpr int WPB = stage_waves<typename Storage<SN>::T, CC, FINAL,                                         \
-                                        (SIDE && increment_storage<SN, SS>())>();                                   \
+        constexpr int WPB = stage_waves<typename Storage<SN>::T, CC, FINAL, keep_p<SIDE>()>();                      \
         const dim3 grid(grid_for(nmax, WPB * (64 / LL))), block(64 * WPB);                                          \
         if (a.g.recon == 0)                                                                                         \
             hipLaunchKernelGGL((stage_kernel<SN, SS, NN, LL, CC, NL, NQ, FINAL, 0, SIDE>), grid, block, 0, st, a);  \
