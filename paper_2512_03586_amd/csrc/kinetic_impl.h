@@ -361,14 +361,9 @@ template <class T> struct MomentAcc {
     }
 };
 
-// Per-lane staging of the explicit stage values f* in LDS between the
-// explicit pass and the relaxation: each lane writes and reads back only its
-// own 16-byte (FP32) slots, so no barrier is needed.
-// Waves per block: 4, or 1 when four waves' LDS staging (f* and the sampled
-// Gaussian, 2 C 64 4 values of type T per wave) would exceed 80 KB.
-template <class T, int C> __host__ __device__ constexpr int waves_per_block() {
-    return 4 * (2 * C * 64 * 4 * (int)sizeof(T)) <= 80 * 1024 ? 4 : 1;
-}
+// Per-lane staging in LDS between the passes over a cell's nodes: each lane
+// writes and reads back only its own 16-byte (FP32) slots, so no barrier is
+// needed.
 
 // LDS of the stage kernels, per wave, in arrays of C x 64 x 4 values: f*
 // (always); the sampled Gaussian of an implicit stage while the kernel's
@@ -879,13 +874,29 @@ __global__ __launch_bounds__((64 * stage_waves<typename Storage<SN>::T, C, FINAL
 
 // f = Mhat(U) at the listed cells (eq. Coupling_FluKin): the corrected sampled
 // Maxwellian, i.e. the corrected Gaussian with Tt = T I.
+#ifndef ESBGK_FILL_G_LDS
+#define ESBGK_FILL_G_LDS 1
+#endif
+// The fill stages the sampled Gaussian in LDS while one array of four waves
+// fits in 40 KB, else evaluates it again for the store.
+template <class T, int C> __host__ __device__ constexpr bool fill_g_lds() {
+    return ESBGK_FILL_G_LDS && 4 * lds_array_bytes<T, C>() <= 40 * 1024;
+}
+template <class T, int C> __host__ __device__ constexpr int fill_waves() {
+    return (!fill_g_lds<T, C>() || 4 * lds_array_bytes<T, C>() <= 80 * 1024) ? 4 : 1;
+}
+template <class T, int W, int C, bool ON> struct FillLds { T g[W][C][64][4]; };
+template <class T, int W, int C> struct FillLds<T, W, C, false> {};
+
 template <class S, int NV, int L, int C>
-__global__ __launch_bounds__((64 * waves_per_block<typename Storage<S>::T, C>())) void fill_maxwellian_kernel(
+__global__ __launch_bounds__((64 * fill_waves<typename Storage<S>::T, C>())) void fill_maxwellian_kernel(
     FillArgs<S> a) {
     using T = typename Storage<S>::T;
-    __shared__ T glds[waves_per_block<T, C>()][C][64][4];
+    constexpr int W = fill_waves<T, C>();
+    constexpr bool GL = fill_g_lds<T, C>();
+    __shared__ FillLds<T, W, C, GL> lds;
     const Geom &g = a.g;
-    const GroupCell gc = group_cell<L, waves_per_block<T, C>()>(a.list, *a.count);
+    const GroupCell gc = group_cell<L, W>(a.list, *a.count);
     if (gc.cell < 0) return;
     const int cell = gc.cell;
     const int lane = (int)(threadIdx.x & 63), wave = (int)(threadIdx.x >> 6);
@@ -900,11 +911,14 @@ __global__ __launch_bounds__((64 * waves_per_block<typename Storage<S>::T, C>())
     GaussEval<T> ge;
     ge.load(gp);
     double Slow[6];
-    gaussian_pass<T, L, C, NV>(glds[wave], nullptr, s, lane, g, ge, (T)gp[GP_PREF], (T)0, (T)1, Slow);
+    T(*gl)[64][4] = nullptr;
+    if constexpr (GL) gl = lds.g[wave];
+    const T prefg = (T)gp[GP_PREF];
+    gaussian_pass<T, L, C, NV>(gl, nullptr, s, lane, g, ge, prefg, (T)0, (T)1, Slow);
     double dc[6] = {0, 0, 0, 0, 0, 0};
     if (g.correction)
-        errbits |= correction_coeffs<T, L, C, NV>(glds[wave], s, lane, g, ge, (T)gp[GP_PREF], Slow, rho, Tm, Tm,
-                                                  0.0, Tm, correction_tol<T>(), dc);
+        errbits |= correction_coeffs<T, L, C, NV>(gl, s, lane, g, ge, prefg, Slow, rho, Tm, Tm, 0.0, Tm,
+                                                  correction_tol<T>(), dc);
     const T d0 = (T)dc[0], d1 = (T)dc[1], d2 = (T)dc[2], d3 = (T)dc[3], d4 = (T)dc[4], d5 = (T)dc[5];
 #pragma unroll
     for (int m = 0; m < C; ++m) {
@@ -912,11 +926,15 @@ __global__ __launch_bounds__((64 * waves_per_block<typename Storage<S>::T, C>())
         if (ch.active && gc.valid) {
             const T b = (ch.vy - ge.uy) * ge.ist;
             const T plin = d1 + d4 * b, pconst = d0 + (d2 + d5 * b) * b;
+            GaussRow<T> gr;
+            if (!GL) gr.set(ge, ch.vy);
             T v[4];
 #pragma unroll
             for (int e = 0; e < 4; ++e) {
                 const T aa = (ch.vx[e] - ge.ux) * ge.ist;
-                const T G = glds[wave][m][lane][e];
+                T G;
+                if constexpr (GL) G = lds.g[wave][m][lane][e];
+                else G = gr.sampled(ge, prefg, ch.vx[e]);
                 v[e] = G + G * ((d3 * aa + plin) * aa + pconst);
             }
             if constexpr (std::is_same<S, bf16_t>::value) {
@@ -1072,7 +1090,7 @@ hipError_t launch_fill(const FillArgs<S> &a, int nmax, hipStream_t st) {
     const Shape sh = shape_for(a.g.nv2);
 #define ESBGK_CASE(NN, LL, CC)                                                                               \
     if ((NN == 0) ? (sh.L == LL && sh.C == CC) : (a.g.nv == NN)) {                                              \
-        constexpr int WPB = waves_per_block<typename Storage<S>::T, CC>();                                                            \
+        constexpr int WPB = fill_waves<typename Storage<S>::T, CC>();                                         \
         hipLaunchKernelGGL((fill_maxwellian_kernel<S, NN, LL, CC>), dim3(grid_for(nmax, WPB * (64 / LL))),    \
                            dim3(64 * WPB), 0, st, a);                                                         \
         return hipGetLastError();                                                                             \
