@@ -233,6 +233,29 @@ def test_fully_kinetic_fp32_matches_oracle(gen, scheme, recon):
     assert rel.max() <= 2e-5
 
 
+# 16-bit stage storage: the mixed form (FP32 state, BF16 increments) and all-BF16,
+# at the velocity grids whose kernels stage the Gaussian in LDS (32^2) and
+# evaluate it again (64^2), on four-quadrant data (discontinuous states, eps from
+# 1e-4 to 1).  The paper fixes no precision for these forms: the bars are about
+# twice the largest pointwise errors measured (mixed 1.0e-4 and 4.4e-4, next to
+# the jumps, where the stored increments are largest; all-BF16 5.5e-2 and
+# 1.4e-2), so that a kernel change that moves them shows up.
+@pytest.mark.parametrize("gen", [FP64_CASES[4][0], FP64_CASES[6][0]], ids=["nv32", "nv64"])
+@pytest.mark.parametrize("precision,bar", [(3, 1e-3), (2, 0.12)], ids=["mixed", "bf16"])
+def test_fully_kinetic_16bit_storage_matches_oracle(gen, precision, bar):
+    d = inputs.riemann4(**gen)
+    nc = d["nx"] * d["ny"]
+    p, eng, st = pair(d, scheme=1, recon=1, precision=precision, mask=np.ones(nc, np.uint8))
+    eng.step(5)
+    st.run(5, update_regime=False)
+    pg = np.stack([t.cpu().numpy() for t in eng.moments()])
+    po = st.prim()
+    rel = np.abs(pg - po) / np.abs(po).max(axis=1, keepdims=True)
+    print(f"precision {precision} nv {gen['nv']}: max rel err {rel.max():.2e}")
+    assert rel.max() <= bar
+    assert eng.stats().error_flags == 0
+
+
 def test_fp32_conservation_and_indicator_consistency():
     """FP32 path with the regime update: the GPU mask equals the oracle
     indicator applied to the GPU's own moments and L1 distances (bit-exact)."""
