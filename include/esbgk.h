@@ -65,8 +65,12 @@ enum { ESBGK_COUPLE_STAGE = 0, ESBGK_COUPLE_STEP = 1 };       /* coupling */
  *              FP32 arithmetic; or MIXED: the state f^n in FP32, FP32
  *              arithmetic, and 16-bit storage of two increments, f^(2) - f^n
  *              and P - f^(3) (P the partial sum of the final combination,
- *              f^(3) kept in FP32), ARS(2,3,3) only.  FP32 velocity sums are
- *              compensated.  Per-cell
+ *              implicit term of the last stage included; f^(3) kept in FP32),
+ *              ARS(2,3,3) only.  FP32 velocity sums are compensated.  The
+ *              implicit term of an earlier stage enters the stage sums as
+ *              (f^(j) - f*_j)/(dt a_jj), equal to (tau/eps)(Ghat_j - f^(j))
+ *              for the exact relaxation, except with 16-bit stage arrays,
+ *              which re-evaluate Ghat_j.  Per-cell
  *              quantities are FP64 always, and so are the 2x2 ES-tensor
  *              algebra and the 6x6 conservation solve.
  *  indicator   PLAIN: the breakdown criteria of Sec. 3.1.2 every step;
