@@ -45,6 +45,11 @@
 #ifndef ESBGK_FINAL_MIN_WAVES
 #define ESBGK_FINAL_MIN_WAVES 4
 #endif
+// mixed form, first implicit stage: keep f^n at the cell in registers for the
+// increment up to this many chunks per lane (else it is read again)
+#ifndef ESBGK_FNR_MAXC
+#define ESBGK_FNR_MAXC 4
+#endif
 
 
 namespace esbgk {
@@ -597,6 +602,10 @@ __global__ __launch_bounds__((64 * stage_waves<typename Storage<SN>::T, C, FINAL
     T base[4], acc[4], qsum[4];  // base: f^n at the cell (final combination: the partial sum P)
     T pacc[4], psum[4];          // side output P of the last implicit stage
     T fsq[4];                    // f*_j of the stage whose implicit term enters: f^n - dt At_j1 L(f^n)
+    // mixed form, first implicit stage: f^n at the cell, the reference of the
+    // stored increment, kept in registers from the explicit pass (small C)
+    constexpr bool FNR = INC && !SIDE && NL == 1 && C <= ESBGK_FNR_MAXC;
+    T fnr[FNR ? C : 1][4];
     // Per-unit work once its transport Lt and centre values cc are known.
     auto unit_body = [&](int m, int l, const Chunk<T> &ch, const T Lt[4], const T cc[4]) {
         const T cl = (T)a.cl[l];
@@ -719,6 +728,10 @@ __global__ __launch_bounds__((64 * stage_waves<typename Storage<SN>::T, C, FINAL
 #pragma unroll
                     for (int e = 0; e < 4; ++e)  // stages transport f^n first; the final combination's base is P
                         base[e] = !FINAL ? cur.c[e] : INC ? cur.c[e] + cur.b[e] : cur.b[e];
+                    if constexpr (FNR) {
+#pragma unroll
+                        for (int e = 0; e < 4; ++e) fnr[m][e] = base[e];
+                    }
                 }
                 T Lt[4];
                 transport_of<T, RECON>(cur, ch, idx, idy, Lt);
@@ -801,6 +814,9 @@ __global__ __launch_bounds__((64 * stage_waves<typename Storage<SN>::T, C, FINAL
                     Storage<SP>::load4((const SP *)a.fout + nb.c, (uint32_t)ch.k0, rv);
                 } else if constexpr (KEEP_P) {
                     Storage<SP>::load4((const SP *)a.sout + nb.c, (uint32_t)ch.k0, rv);
+                } else if constexpr (FNR) {
+#pragma unroll
+                    for (int e = 0; e < 4; ++e) rv[e] = fnr[m][e];
                 } else if constexpr (INC) {
                     Storage<SN>::load4((const SN *)a.fn + nb.c, (uint32_t)ch.k0, rv);
                 }
