@@ -46,9 +46,10 @@
 #define ESBGK_FINAL_MIN_WAVES 4
 #endif
 // mixed form, first implicit stage: keep f^n at the cell in registers for the
-// increment up to this many chunks per lane (else it is read again)
+// increment up to this many chunks per lane (else it is read again; measured
+// faster at every instantiated size, 4 to 16 chunks)
 #ifndef ESBGK_FNR_MAXC
-#define ESBGK_FNR_MAXC 4
+#define ESBGK_FNR_MAXC 16
 #endif
 
 
@@ -603,7 +604,7 @@ __global__ __launch_bounds__((64 * stage_waves<typename Storage<SN>::T, C, FINAL
     T pacc[4], psum[4];          // side output P of the last implicit stage
     T fsq[4];                    // f*_j of the stage whose implicit term enters: f^n - dt At_j1 L(f^n)
     // mixed form, first implicit stage: f^n at the cell, the reference of the
-    // stored increment, kept in registers from the explicit pass (small C)
+    // stored increment, kept in registers from the explicit pass
     constexpr bool FNR = INC && !SIDE && NL == 1 && C <= ESBGK_FNR_MAXC;
     T fnr[FNR ? C : 1][4];
     // Per-unit work once its transport Lt and centre values cc are known.
