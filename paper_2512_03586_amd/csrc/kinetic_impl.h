@@ -370,7 +370,7 @@ template <class T> struct MomentAcc {
 // Per-lane staging in LDS between the passes over a cell's nodes: each lane
 // writes and reads back only its own 16-byte (FP32) slots, so no barrier is
 // needed.
-
+//
 // LDS of the stage kernels, per wave, in arrays of C x 64 x 4 values: f*
 // (always); the sampled Gaussian of an implicit stage while the kernel's
 // arrays for four waves fit in 80 KB (stage 2 up to nv = 48, the last stage of
@@ -427,11 +427,12 @@ struct StageLds : LdsGauss<T, stage_waves<T, C, FINAL, KEEP_P>(), C, !FINAL && g
 //   Ghat = Gtilde (1 + dc . psi)
 // with dc chosen so that Ghat's discrete moments of psi equal the continuous
 // ones t = (rho, 0, 0, rho Tt/T).  Pass 1 (gaussian_pass) evaluates Gtilde at
-// every node into LDS and accumulates its six discrete moments of order <= 2
-// (compensated); r = t - those.  When |r|/rho is below tol the moment matrix is
-// replaced by the continuous Gaussian's (closed form, residual second order in
-// the quadrature error); otherwise the nine higher discrete moments are summed
-// from LDS and the exact discrete Gram matrix is solved.  Returns error bits.
+// every node (into LDS when glds is given) and accumulates its six discrete
+// moments of order <= 2 (compensated); r = t - those.  When |r|/rho is below
+// tol the moment matrix is replaced by the continuous Gaussian's (closed form,
+// residual second order in the quadrature error); otherwise the nine higher
+// discrete moments are summed (from LDS, or over Gtilde evaluated again) and
+// the exact discrete Gram matrix is solved.  Returns error bits.
 template <class T, int L, int C, int NV>
 __device__ inline int correction_coeffs(const T (*glds)[64][4], int s, int lane, const Geom &g,
                                         const GaussEval<T> &ge, T pref, const double Slow[6], double rho,
