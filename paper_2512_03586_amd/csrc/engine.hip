@@ -94,7 +94,7 @@ int validate(const esbgk_config *c) {
 }
 
 struct Layout {
-    size_t f[3], fP, U[4], gp, eps, l1, prim, mask, mask_old, cls, kin, buf, newk, blockcounts, counts, err,
+    size_t f[3], fP, U[4], D[3], gp, eps, l1, prim, mask, mask_old, cls, kin, buf, newk, blockcounts, counts, err,
         bad, kin_total;
     // learned indicator (indicator == LEARNED only)
     size_t derived, pmask, lcount;
@@ -110,6 +110,8 @@ Layout layout(const esbgk_config *c) {
     // partial sum of the final combination (ARS(2,3,3)), state precision and at least FP32
     L.fP = take(c->scheme == ESBGK_ARS233 ? nc * nv2 * std::max<size_t>(4, state_elem(c->precision)) : 0);
     for (int q = 0; q < 4; ++q) L.U[q] = take(4 * nc * sizeof(double));
+    // Euler flux divergences of the step's states, SoA [4][nc]
+    for (int q = 0; q < 3; ++q) L.D[q] = take(4 * nc * sizeof(double));
     // Gaussian parameters of stage 2, read by stage 3 when the stage arrays are BF16
     L.gp = take(stage_gauss_params(c->precision) ? (size_t)GP_N * nc * sizeof(double) : 0);
     L.eps = take(nc * sizeof(double));
@@ -151,6 +153,8 @@ struct esbgk_ctx {
     void *fP = nullptr;
     double *U[4]{};
     double *gp = nullptr;  // BF16 stage arrays only
+    double *D[3]{};        // Euler flux divergences of the step's states
+    bool dvalid[3]{};      // D[j] holds the divergence of this step's U^(j)
     double *eps = nullptr, *l1 = nullptr, *prim = nullptr;
     uint8_t *mask = nullptr, *mask_old = nullptr, *cls = nullptr;
     int *kin = nullptr, *buf = nullptr, *newk = nullptr, *blockcounts = nullptr, *counts = nullptr,
@@ -320,8 +324,17 @@ int euler_stage(esbgk_ctx *c, int i, hipStream_t st, double *Uout) {
     e.Un = c->U[0];
     const double *rowt = i < 3 ? &c->At[3 * i] : c->bt;
     const int nprev = i < 3 ? i : 3;
+    // the divergence of the newest state U^(i-1) is formed now and stored;
+    // those of earlier states were stored by the earlier stages of this step
+    e.jnew = -1;
     for (int j = 0; j < nprev; ++j)
-        if (rowt[j] != 0.0) { e.Uj[e.nj] = c->U[j]; e.cj[e.nj] = rowt[j]; ++e.nj; }
+        if (rowt[j] != 0.0) {
+            if (j == i - 1) e.jnew = e.nj;
+            else if (!c->dvalid[j]) return fail(ESBGK_EINVAL, "tableau not supported by the Euler stage");
+            e.Uj[e.nj] = c->U[j]; e.Dj[e.nj] = c->D[j]; e.cj[e.nj] = rowt[j]; ++e.nj;
+        }
+    e.Dout = c->D[i - 1];
+    c->dvalid[i - 1] = true;
     e.Uout = Uout;
     e.mask = c->mask;
     HIPCHK(launch_euler(e, st));
@@ -356,6 +369,7 @@ template <class SN, class SS> int run_step(esbgk_ctx *c, hipStream_t st) {
     const size_t nc = (size_t)c->nc;
     const bool loc = c->cfg.coupling == ESBGK_COUPLE_STEP;
     int rc;
+    for (bool &v : c->dvalid) v = false;
     // ---- regime update (Algorithm 1: at the start of every step)
     if (c->cfg.indicator == ESBGK_IND_PLAIN) {
         std::swap(c->mask_old, c->mask);  // the indicator writes the new mask from the previous one
@@ -478,6 +492,7 @@ int esbgk_create(const esbgk_config *cfg, void *d_workspace, size_t bytes, esbgk
     for (int q = 0; q < 3; ++q) c->f[q] = w + L.f[q];
     c->fP = w + L.fP;
     for (int q = 0; q < 4; ++q) c->U[q] = (double *)(w + L.U[q]);
+    for (int q = 0; q < 3; ++q) c->D[q] = (double *)(w + L.D[q]);
     c->gp = stage_gauss_params(cfg->precision) ? (double *)(w + L.gp) : nullptr;
     c->eps = (double *)(w + L.eps);
     c->l1 = (double *)(w + L.l1);

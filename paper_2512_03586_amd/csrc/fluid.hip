@@ -52,21 +52,24 @@ __device__ inline void euler_face_vals(const double st[4][4], int d, int recon, 
 }
 
 // U^(i) = U^n - dt sum_j c_j Phi(U^(j)) on fluid cells (eqs. RKEuler, RKEuler_2).
-// One 8 x 8 tile of cells per 4-wavefront block: the U^(j) tiles with their
-// 2-cell periodic halo are staged in LDS, every face flux of the tile is
-// computed once (9 x 8 faces per direction and stage array, one thread per
-// face, so the divide / square-root chains of many faces interleave), and
-// each cell takes the difference of its two faces per direction.
+// One 8 x 8 tile of cells per 4-wavefront block.  Only the newest state's
+// flux divergence is formed: its tile with the 2-cell periodic halo is staged
+// in LDS, every face flux of the tile is computed once (9 x 8 faces per
+// direction, one thread per face, so the divide / square-root chains of many
+// faces interleave), each cell takes the difference of its two faces per
+// direction and stores it for the later stages of the step; the divergences
+// of earlier states are read back (each state's is formed once per step).
 constexpr int ET = 8, EH = 2, EW = ET + 2 * EH, ENT = 256, ENJ = 3;
 constexpr int EFACES = ET * (ET + 1);  // faces per direction
 
 __global__ __launch_bounds__(ENT) void euler_stage_kernel(EulerArgs a) {
-    __shared__ double u[ENJ][4][EW][EW];
-    __shared__ double fx[ENJ][4][ET][ET + 1];
-    __shared__ double fy[ENJ][4][ET + 1][ET];
+    __shared__ double u[1][4][EW][EW];
+    __shared__ double fx[1][4][ET][ET + 1];
+    __shared__ double fy[1][4][ET + 1][ET];
     const int tid = (int)threadIdx.x;
     const int i0 = (int)blockIdx.x * ET, j0 = (int)blockIdx.y * ET;
     const int nx = a.nx, ny = a.ny, nj = a.nj;
+    const int jn = a.jnew;  // the one state whose divergence is formed here (-1: none)
     const size_t nc = (size_t)a.nc;
     // cell of threads 0..63
     const int tx = tid % ET, ty = tid / ET;
@@ -75,18 +78,19 @@ __global__ __launch_bounds__(ENT) void euler_stage_kernel(EulerArgs a) {
     const size_t cell = own ? (size_t)j * nx + i : 0;
     const bool fluid = own && !a.mask[cell];
     if (!__syncthreads_or(fluid)) return;  // whole tile kinetic (or outside)
-    for (int t = tid; t < nj * EW * EW; t += ENT) {
-        const int jj = t / (EW * EW), r = t % (EW * EW);
+    const int nnew = jn >= 0 ? 1 : 0;
+    for (int t = tid; t < nnew * EW * EW; t += ENT) {
+        const int jj = 0, r = t;
         const int li = r % EW, lj = r / EW;
         const int gi = wrapc(i0 + li - EH, nx), gj = wrapc(j0 + lj - EH, ny);
         const size_t c = (size_t)gj * nx + gi;
-        const double *U = a.Uj[jj];
+        const double *U = a.Uj[jn];
 #pragma unroll
         for (int q = 0; q < 4; ++q) u[jj][q][lj][li] = U[q * nc + c];
     }
     __syncthreads();
-    for (int t = tid; t < nj * 2 * EFACES; t += ENT) {
-        const int jj = t / (2 * EFACES), r = t % (2 * EFACES);
+    for (int t = tid; t < nnew * 2 * EFACES; t += ENT) {
+        const int jj = 0, r = t;
         const int d = r / EFACES, k = r % EFACES;
         double st[4][4], F[4];
         if (d == 0) {
@@ -122,10 +126,22 @@ __global__ __launch_bounds__(ENT) void euler_stage_kernel(EulerArgs a) {
         for (int q = 0; q < 4; ++q) s[q] = a.Un[q * nc + cell];
         for (int jj = 0; jj < nj; ++jj) {
             const double c = a.dt * a.cj[jj];
+            double D[4];
+            if (jj == jn) {
 #pragma unroll
-            for (int q = 0; q < 4; ++q)
-                s[q] -= c * ((fx[jj][q][ty][tx + 1] - fx[jj][q][ty][tx]) * idx +
-                             (fy[jj][q][ty + 1][tx] - fy[jj][q][ty][tx]) * idy);
+                for (int q = 0; q < 4; ++q)
+                    D[q] = (fx[0][q][ty][tx + 1] - fx[0][q][ty][tx]) * idx +
+                           (fy[0][q][ty + 1][tx] - fy[0][q][ty][tx]) * idy;
+                if (a.Dout) {
+#pragma unroll
+                    for (int q = 0; q < 4; ++q) a.Dout[q * nc + cell] = D[q];
+                }
+            } else {
+#pragma unroll
+                for (int q = 0; q < 4; ++q) D[q] = a.Dj[jj][q * nc + cell];
+            }
+#pragma unroll
+            for (int q = 0; q < 4; ++q) s[q] -= c * D[q];
         }
 #pragma unroll
         for (int q = 0; q < 4; ++q) a.Uout[q * nc + cell] = s[q];
@@ -428,7 +444,9 @@ __global__ void dilate_y_kernel(const uint8_t *tmp, uint8_t *out, int nx, int ny
 
 hipError_t launch_euler(const EulerArgs &a, hipStream_t st) {
     const dim3 grid((unsigned)((a.nx + ET - 1) / ET), (unsigned)((a.ny + ET - 1) / ET));
-    if (a.nj < 0 || a.nj > ENJ) return hipErrorInvalidValue;
+    if (a.nj < 0 || a.nj > ENJ || a.jnew >= a.nj) return hipErrorInvalidValue;
+    for (int j = 0; j < a.nj; ++j)
+        if (j != a.jnew && !a.Dj[j]) return hipErrorInvalidValue;
     hipLaunchKernelGGL(euler_stage_kernel, grid, dim3(ENT), 0, st, a);
     return hipGetLastError();
 }

@@ -80,13 +80,19 @@ template <class S> struct MomArgs {
     int nc;
 };
 
+// Euler stage on fluid cells: Uout = Un - dt sum_j cj[j] D_j, D_j the flux
+// divergence of state Uj[j].  The divergence of state jnew is formed from its
+// stencil (and stored to Dout when given); every other D_j was stored by an
+// earlier stage of the step and is read from Dj[j].
 struct EulerArgs {
     int nx, ny, nc, recon;
     double dx, dy, dt;
     const double *Un;
     const double *Uj[3];
+    const double *Dj[3];
     double cj[3];
-    int nj;
+    int nj, jnew;
+    double *Dout;
     double *Uout;
     const uint8_t *mask;
 };
