@@ -73,3 +73,51 @@ def test_sampled_cell_step_matches_oracle_patch(gpu_run, cell):
     assert np.all(np.abs(Ug - Uo) <= 2e-5 * scale), (cell, Ug, Uo)
     fg = f1[cell].cpu().numpy()
     assert np.abs(fg - st.f[c]).max() <= 2e-5 * np.abs(st.f[c]).max()
+
+
+# ---------------------------------------------------------------- Euler, 512^2
+# The Euler stage switches to 16 x 16 cell tiles on grids of at least 1024 such
+# tiles.  A fully fluid 512^2 run (FP64) takes that path; each Euler stage reads
+# cells within 2, so after one step a cell depends on cells within 6 and the
+# same patch argument holds.  Bar: the FP64 path's, 1e-10 relative on U.
+NXE = 512
+
+
+@pytest.fixture(scope="module")
+def gpu_euler_run():
+    if not torch.cuda.is_available():
+        pytest.fail("no GPU visible")
+    from paper_2512_03586_amd import esbgk as E
+    E.lib()
+    oracle.build(force=False)
+    d = inputs.riemann4(nx=NXE, ny=NXE, nv=8, vmax=VMAX, seed=3)
+    cfg = E.make_config(NXE, NXE, 8, VMAX, precision=E.FP64, indicator=E.IND_FROZEN, scheme=E.ARS233,
+                        recon=E.MINMOD2, eta=1e-2, delta=1e-3, dt=0.25 / NXE / 2.5)
+    eng = E.Engine(cfg)
+    eng.set_state(d["rho"], d["ux"], d["uy"], d["T"], d["eps"])
+    eng.set_mask(np.zeros(NXE * NXE, np.uint8))
+    eng.step(3)
+    U0 = eng.conserved().cpu().numpy()
+    eng.step(1)
+    U1 = eng.conserved().cpu().numpy()
+    st = eng.stats()
+    assert st.error_flags == 0
+    return d, U0, U1, st.dt
+
+
+@pytest.mark.parametrize("cell", [0, NXE - 1, NXE * (NXE // 2) + NXE // 2, NXE * NXE - 1, 17 * NXE + 300,
+                                  255 * NXE + 256, 256 * NXE + 255])
+def test_euler_16x16_tiles_match_oracle_patch(gpu_euler_run, cell):
+    d, U0, U1, dt = gpu_euler_run
+    i0, j0 = cell % NXE, cell // NXE
+    w = 2 * R + 1
+    ii = (i0 + np.arange(-R, R + 1)) % NXE
+    jj = (j0 + np.arange(-R, R + 1)) % NXE
+    idx = (jj[:, None] * NXE + ii[None, :]).ravel()
+    p = oracle.Problem(nx=w, ny=w, nv=8, vmax=VMAX, lx=w / NXE, ly=w / NXE, scheme=1, recon=1, dt=dt,
+                       eta=1e-2, delta=1e-3)
+    st = oracle.State(p, U0[:, idx], d["eps"][idx], mask=np.zeros(w * w, np.uint8))
+    st.run(1, update_regime=False)
+    c = R * w + R
+    scale = np.abs(U1).max(axis=1)
+    assert np.all(np.abs(U1[:, cell] - st.U[:, c]) <= 1e-10 * scale), (cell, U1[:, cell], st.U[:, c])
